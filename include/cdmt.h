@@ -1,0 +1,142 @@
+/*
+ * cdmt.h -- C ABI of the MI355X coherent-dedispersion library.
+ *
+ * Coherent dedispersion of channelised dual-polarisation complex voltages to
+ * many dispersion-measure (DM) trials, after Bassa, Pleunis & Hessels (2016),
+ * "Enabling pulsar and fast transient searches using coherent dedispersion".
+ * Notation follows the paper: n_s subbands, n_c channels per subband, forward
+ * transform size N_bin (nfft), backward size M_bin = N_bin / n_c, overlap of
+ * n_d channel samples (noverlap = n_d * n_c subband samples).
+ *
+ * Ownership: the caller owns every device buffer (voltages, workspace,
+ * output).  The library never allocates device memory at run time and never
+ * copies between host and device; the DM list is passed to the kernels by
+ * value.  A plan is a host object.
+ *
+ * Errors: every entry point returns CDMT_OK (0) or a negative status and, on
+ * error, writes nothing to device memory.  Kernel launch failures are reported
+ * as CDMT_E_DEVICE.  Calls that enqueue work are asynchronous on the given HIP
+ * stream (NULL = the default stream) and return once the work is enqueued.
+ * Concurrent calls with the same workspace race; distinct workspaces may run
+ * concurrently on different streams.
+ */
+#ifndef CDMT_H
+#define CDMT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cdmt_plan_s *cdmt_plan_t;
+
+enum cdmt_status {
+    CDMT_OK = 0,
+    CDMT_E_ARG = -1,         /* null pointer, non-finite value, bad option      */
+    CDMT_E_SHAPE = -2,       /* sizes violate the method's constraints          */
+    CDMT_E_WORKSPACE = -3,   /* workspace smaller than cdmt_workspace_size      */
+    CDMT_E_DEVICE = -4,      /* HIP error (no device, launch failure)           */
+    CDMT_E_UNSUPPORTED = -5  /* valid for the method, not built in this library */
+};
+
+enum cdmt_opt {
+    CDMT_OPT_INPUT = 0,      /* 0: complex float32 (default), 1: complex int8           */
+    CDMT_OPT_CHIRP_REF = 1,  /* 0: nu0 = channel centre (default), 1: subband centre    */
+    CDMT_OPT_SIGN = 2,       /* -1: dedisperse (default), +1: multiply by Eq. 1 as is   */
+    CDMT_OPT_PRECISION = 3,  /* 0: FP32 (default); others: CDMT_E_UNSUPPORTED for now    */
+    CDMT_OPT_DM_TILE = 4     /* DM trials per workgroup pass, 1..16 (default 4)         */
+};
+
+/*
+ * Create a plan.  Sec. 3 (initialisation before Alg. 1's loops): the user
+ * chooses n_c, N_bin and n_d; the frequency setup is n_s adjacent subbands of
+ * width bw_sub_mhz (= complex sample rate in MHz, Nyquist sampling, Sec. 3),
+ * upper sideband, in increasing frequency, centred on f_centre_mhz.  Subband s
+ * is centred on f_centre + (s - (n_s-1)/2) * bw.
+ *
+ *   nsub       n_s >= 1
+ *   nfft       N_bin, power of two in [2^10, 2^17]
+ *   noverlap   n_d * n_c subband samples; multiple of 2*nchan, < nfft
+ *              (Sec. 2: sections overlap by n_d n_c samples, n_d/2 channel
+ *              samples discarded at each edge)
+ *   nchan      n_c, power of two with M_bin = nfft/nchan in [64, 8192]
+ *   ndec       output samples summed per filterbank sample, >= 1, must
+ *              divide M_bin - n_d
+ * Requires bw_sub_mhz > 0 and f_centre - nsub*bw/2 > 0.
+ * On success *out holds a new plan (free with cdmt_destroy).
+ */
+int cdmt_plan(cdmt_plan_t *out, int nsub, double f_centre_mhz, double bw_sub_mhz,
+              int nfft, int noverlap, int nchan, int ndec);
+
+/* Set an option (enum cdmt_opt).  CDMT_E_ARG for an unknown option or value. */
+int cdmt_plan_set(cdmt_plan_t plan, int opt, int value);
+
+/* Read an option back into *value. */
+int cdmt_plan_get(cdmt_plan_t plan, int opt, int *value);
+
+/*
+ * Overlap needed for a DM range (Sec. 2: n_d = r t_d / n_c with t_d from
+ * Eq. 2 for the lowest channel, or the lowest subband when chirp_ref = 1),
+ * in subband samples, rounded up to a multiple of 2*nchan*ndec.
+ * f_lo_mhz is the lower edge of the lowest subband; dm_max >= 0.
+ */
+int cdmt_noverlap_for(double f_lo_mhz, double bw_sub_mhz, double dm_max, int nchan, int ndec,
+                      int chirp_ref, int *noverlap_out);
+
+/*
+ * Shapes for nblock blocks (Sec. 3, the block loop of Alg. 1):
+ *   ntime_in  = nblock*(nfft - noverlap) + noverlap input samples per subband
+ *   ntime_out = nblock*(M_bin - n_d)/ndec filterbank samples
+ *   nchan_out = nsub*nchan
+ * Output sample t covers input samples noverlap/2 + t*nchan*ndec + [0, nchan*ndec).
+ * Any pointer may be NULL.
+ */
+int cdmt_output_shape(cdmt_plan_t plan, int nblock, long long *ntime_in, long long *ntime_out,
+                      int *nchan_out);
+
+/* Device workspace in bytes for nblock blocks (spectra of both polarisations
+ * plus the four-step intermediate). */
+int cdmt_workspace_size(cdmt_plan_t plan, int nblock, size_t *bytes);
+
+/*
+ * Forward stage of Alg. 1 for nblock blocks: unpack and segment (Sec. 3), the
+ * forward FFT of N_bin per subband, block and polarisation, and the swap of
+ * halves per subband.  The spectra stay in the workspace for
+ * cdmt_dedisperse_spectra.
+ *   voltages  device, [nsub][ntime_in][2 pol X,Y][re, im], float32 or int8
+ *             (CDMT_OPT_INPUT), ntime_in from cdmt_output_shape
+ */
+int cdmt_forward(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const void *voltages,
+                 int nblock, void *hip_stream);
+
+/*
+ * DM stage of Alg. 1 on spectra left by cdmt_forward with the same nblock:
+ * for every DM trial, the complex multiplication with the transfer function
+ * of every channel (Sec. 2, Eq. 1), the swap of halves per channel, the
+ * backward FFT of M_bin, unpadding (n_d/2 per edge), detection
+ * |X|^2 + |Y|^2, the sum of ndec consecutive samples, and the transpose to
+ * [time][channel] with channels in decreasing frequency.
+ *   dm_list   host, ndm values in pc cm^-3 (finite; read during the call only)
+ *   out       device float32 [ndm][ntime_out][nsub*nchan]
+ * ndm = 0 is a no-op.
+ */
+int cdmt_dedisperse_spectra(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nblock,
+                            const double *dm_list, int ndm, float *out, void *hip_stream);
+
+/* cdmt_forward followed by cdmt_dedisperse_spectra: the whole of Alg. 1's
+ * compute for nblock blocks and ndm DM trials. */
+int cdmt_dedisperse(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const void *voltages,
+                    int nblock, const double *dm_list, int ndm, float *out, void *hip_stream);
+
+/* Free a plan (NULL is accepted). */
+void cdmt_destroy(cdmt_plan_t plan);
+
+/* Static description of a status code. */
+const char *cdmt_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDMT_H */
