@@ -1,0 +1,200 @@
+#!/usr/bin/env python
+"""Throughput of coherent dedispersion to many DM trials on one MI355X.
+
+Workload (default): LOFAR-HBA-shaped, 288 subbands of 195.3125 kHz centred
+on 138 MHz, 10.02 s of dual-polarisation complex int8 voltages (Gaussian,
+sigma 16, generated in device memory from a fixed seed), nfft 65536 with
+noverlap 15360, 16 channels per subband, x8 downsampling, 128 DM trials
+0..63.5.  One step = the whole path for that batch: the forward FFT of every
+block and subband, then every DM trial (transfer function, backward FFT,
+detection, downsampling, transpose) into an FP32 filterbank
+[128][15288][4608] that stays in device memory.
+
+Metric: DM trials x seconds of data processed per second of wall time.
+Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "DM-trials×data-sec per sec (LOFAR-shaped), %HBM peak; mixed vs FP32 plain"
+HBM_PEAK_GBS = 8000.0
+# Non-packed FP32 vector issue: 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz.
+VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def fused_flops_per_bin(m: int) -> float:
+    """Nominal flops per spectral bin per DM of the fused kernel: for both
+    polarisations, complex multiply (6), backward FFT (5 log2 M per point),
+    detection (3)."""
+    import math
+    return 2 * (6 + 5 * math.log2(m) + 3)
+
+
+def cpu_baseline(w, x_dev, npairs: int, threads: int):
+    """Oracle (FP64, C) on a bounded sample of (subband, block) pairs with all
+    DMs, extrapolated linearly to the whole job."""
+    import numpy as np
+
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+
+    cfg = oracle.Config(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+    pairs = []
+    for i in range(npairs):
+        s = (i * 97) % w.nsub
+        b = (i * 7) % w.nblock
+        pairs.append((s, b))
+    subs = sorted({s for s, _ in pairs})
+    host = {s: x_dev[s].cpu().numpy() for s in subs}
+
+    def one(sb):
+        s, b = sb
+        xs = host[s][None]
+        c1 = oracle.Config(1, cfg.sub_centre(s), w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+        return oracle.subband_block(c1, xs, 0, b, list(w.dms))
+
+    oracle._load()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, pairs))
+    dt = time.perf_counter() - t0
+    total_pairs = w.nsub * w.nblock
+    full_seconds = dt * total_pairs / len(pairs)
+    value = len(w.dms) * w.data_seconds / full_seconds
+    return {"value": value, "unit": "DM-s/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(pairs)} (subband, block) pairs x {len(w.dms)} DMs of the "
+                      f"{total_pairs}-pair job, {dt:.1f} s wall on {threads} threads, "
+                      f"extrapolated linearly"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="lofar-hba-288sub-128dm")
+    ap.add_argument("--dm-tile", type=int, default=None)
+    ap.add_argument("--chirp-ref", choices=["channel", "subband"], default="channel")
+    ap.add_argument("--cpu-pairs", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1607_00909_amd as cdmt
+    from paper_1607_00909_amd import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    w = synth.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    log(f"workload {w.name}: generating {w.nsub}x{w.ntime_in} {w.input_kind} voltages on device")
+    x = synth.device_noise(w.input_kind, w.nsub, w.ntime_in, w.sigma, w.seed, dev)
+    kind = cdmt.INPUT_CI8 if w.input_kind == "ci8" else cdmt.INPUT_CF32
+    chirp_ref = cdmt.CHIRP_CHANNEL if args.chirp_ref == "channel" else cdmt.CHIRP_SUBBAND
+    plan = cdmt.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                     input_kind=kind, chirp_ref=chirp_ref, dm_tile=args.dm_tile)
+    dm_tile = cdmt.cdmt_plan_get(plan.handle, cdmt.CDMT_OPT_DM_TILE)
+    ws = plan.workspace(w.nblock, dev)
+    _, ntout, nch = plan.shape(w.nblock)
+    out = torch.empty((len(w.dms), ntout, nch), dtype=torch.float32, device=dev)
+    dms = list(w.dms)
+    stream = torch.cuda.current_stream()
+    log(f"workspace {ws.numel() / 1e9:.2f} GB, output {out.numel() * 4 / 1e9:.2f} GB, "
+        f"dm_tile {dm_tile}")
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.forward(x, w.nblock, ws)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.dedisperse_spectra(w.nblock, dms, out, ws)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    fwd_ms = [e[0].elapsed_time(e[1]) for e in events]
+    fus_ms = [e[1].elapsed_time(e[2]) for e in events]
+    log(f"timed {args.steps} steps in {elapsed:.3f} s")
+
+    ndm = len(dms)
+    value = ndm * w.data_seconds * args.steps / elapsed
+    fus_avg = sum(fus_ms) / len(fus_ms) / 1e3
+    fwd_avg = sum(fwd_ms) / len(fwd_ms) / 1e3
+    bins = w.nblock * w.nsub * w.nfft
+    flops = bins * ndm * fused_flops_per_bin(w.m)
+    spec_bytes = bins * 16
+    ntiles = -(-ndm // dm_tile)
+    fused_bytes = spec_bytes * ntiles + out.numel() * 4
+    fwd_bytes = x.numel() * x.element_size() + 3 * spec_bytes
+    achieved = flops / fus_avg / 1e12
+    line = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "DM-s/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nsub": w.nsub, "f_centre_mhz": w.f_centre,
+                   "bw_sub_mhz": w.bw, "nfft": w.nfft, "noverlap": w.noverlap,
+                   "nchan": w.nchan, "ndec": w.ndec, "nblock": w.nblock, "ndm": ndm,
+                   "data_seconds": round(w.data_seconds, 6), "input": w.input_kind,
+                   "chirp_ref": args.chirp_ref, "dm_tile": dm_tile, "precision": "fp32",
+                   "parallelism": "none"},
+        "roofline": {"kernel": "fused_dedisperse", "bound": "alu",
+                     "achieved": round(achieved, 3), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4),
+                     "traffic": None,
+                     "hbm_algorithmic_GBs": round(fused_bytes / fus_avg / 1e9, 1),
+                     "hbm_frac": round(fused_bytes / fus_avg / 1e9 / HBM_PEAK_GBS, 4)},
+        "kernels_ms": {"forward (fwd_col+fwd_row)": round(fwd_avg * 1e3, 3),
+                       "fused_dedisperse": round(fus_avg * 1e3, 3),
+                       "forward_algorithmic_GBs": round(fwd_bytes / fwd_avg / 1e9, 1)},
+        "realtime_factor": round(w.data_seconds / (elapsed / args.steps), 2),
+    }
+    if not args.no_cpu_baseline:
+        threads = min(16, os.cpu_count() or 1)
+        log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads")
+        line["cpu_baseline"] = cpu_baseline(w, x, args.cpu_pairs, threads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+"""Python binding of the MI355X coherent-dedispersion library (libcdmt.so).
+
+Thin ctypes layer over the C ABI in include/cdmt.h: the functions below have
+the C names and only marshal arguments (device pointers from torch tensors,
+HIP streams from torch streams).  Every step of the computation runs in the
+library's HIP kernels.  If the library has not been built, the first call
+raises; there is no fallback.
+
+Method: coherent dedispersion to many DM trials (Bassa, Pleunis & Hessels
+2016, Sec. 2-3, Alg. 1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcdmt.so")
+
+# enum cdmt_status
+CDMT_OK, CDMT_E_ARG, CDMT_E_SHAPE, CDMT_E_WORKSPACE, CDMT_E_DEVICE, CDMT_E_UNSUPPORTED = \
+    0, -1, -2, -3, -4, -5
+# enum cdmt_opt
+CDMT_OPT_INPUT, CDMT_OPT_CHIRP_REF, CDMT_OPT_SIGN, CDMT_OPT_PRECISION, CDMT_OPT_DM_TILE = \
+    0, 1, 2, 3, 4
+INPUT_CF32, INPUT_CI8 = 0, 1
+CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
+
+# every symbol include/cdmt.h declares
+EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
+           "cdmt_output_shape", "cdmt_workspace_size", "cdmt_forward",
+           "cdmt_dedisperse_spectra", "cdmt_dedisperse", "cdmt_destroy", "cdmt_status_string")
+
+_lib = None
+_lock = threading.Lock()
+
+
+class CdmtError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {cdmt_status_string(status)} ({status})")
+
+
+def load():
+    """Load libcdmt.so (after torch, so both use the same HIP runtime)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1607_00909_amd.build`")
+        try:
+            import torch  # noqa: F401  (load torch's HIP runtime first)
+        except ImportError:
+            pass
+        lib = ctypes.CDLL(LIB_PATH)
+        P, I, D, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+        LL = ctypes.c_longlong
+        lib.cdmt_plan.argtypes = [ctypes.POINTER(P), I, D, D, I, I, I, I]
+        lib.cdmt_plan_set.argtypes = [P, I, I]
+        lib.cdmt_plan_get.argtypes = [P, I, ctypes.POINTER(I)]
+        lib.cdmt_noverlap_for.argtypes = [D, D, D, I, I, I, ctypes.POINTER(I)]
+        lib.cdmt_output_shape.argtypes = [P, I, ctypes.POINTER(LL), ctypes.POINTER(LL),
+                                          ctypes.POINTER(I)]
+        lib.cdmt_workspace_size.argtypes = [P, I, ctypes.POINTER(Z)]
+        lib.cdmt_forward.argtypes = [P, P, Z, P, I, P]
+        lib.cdmt_dedisperse_spectra.argtypes = [P, P, Z, I, ctypes.POINTER(D), I, P, P]
+        lib.cdmt_dedisperse.argtypes = [P, P, Z, P, I, ctypes.POINTER(D), I, P, P]
+        lib.cdmt_destroy.argtypes = [P]
+        lib.cdmt_destroy.restype = None
+        lib.cdmt_status_string.argtypes = [I]
+        lib.cdmt_status_string.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if not hasattr(lib, name):
+                raise RuntimeError(f"{LIB_PATH} does not export {name}")
+        _lib = lib
+        return lib
+
+
+def _check(status: int, where: str) -> None:
+    if status != CDMT_OK:
+        raise CdmtError(status, where)
+
+
+def cdmt_status_string(status: int) -> str:
+    return load().cdmt_status_string(int(status)).decode()
+
+
+# -------------------------------------------------------------- C names ----
+
+def cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec) -> int:
+    h = ctypes.c_void_p()
+    _check(load().cdmt_plan(ctypes.byref(h), nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap,
+                            nchan, ndec), "cdmt_plan")
+    return h.value
+
+
+def cdmt_plan_set(plan, opt, value) -> None:
+    _check(load().cdmt_plan_set(plan, opt, value), "cdmt_plan_set")
+
+
+def cdmt_plan_get(plan, opt) -> int:
+    v = ctypes.c_int()
+    _check(load().cdmt_plan_get(plan, opt, ctypes.byref(v)), "cdmt_plan_get")
+    return v.value
+
+
+def cdmt_noverlap_for(f_lo_mhz, bw_sub_mhz, dm_max, nchan, ndec, chirp_ref=CHIRP_CHANNEL) -> int:
+    v = ctypes.c_int()
+    _check(load().cdmt_noverlap_for(f_lo_mhz, bw_sub_mhz, dm_max, nchan, ndec, chirp_ref,
+                                    ctypes.byref(v)), "cdmt_noverlap_for")
+    return v.value
+
+
+def cdmt_output_shape(plan, nblock):
+    a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+    _check(load().cdmt_output_shape(plan, nblock, ctypes.byref(a), ctypes.byref(b),
+                                    ctypes.byref(c)), "cdmt_output_shape")
+    return a.value, b.value, c.value
+
+
+def cdmt_workspace_size(plan, nblock) -> int:
+    v = ctypes.c_size_t()
+    _check(load().cdmt_workspace_size(plan, nblock, ctypes.byref(v)), "cdmt_workspace_size")
+    return v.value
+
+
+def _dm_array(dms):
+    dms = [float(d) for d in dms]
+    return (ctypes.c_double * max(1, len(dms)))(*dms), len(dms)
+
+
+def cdmt_forward(plan, workspace, ws_bytes, voltages, nblock, stream) -> None:
+    _check(load().cdmt_forward(plan, workspace, ws_bytes, voltages, nblock, stream),
+           "cdmt_forward")
+
+
+def cdmt_dedisperse_spectra(plan, workspace, ws_bytes, nblock, dms, out, stream) -> None:
+    arr, n = _dm_array(dms)
+    _check(load().cdmt_dedisperse_spectra(plan, workspace, ws_bytes, nblock, arr, n, out, stream),
+           "cdmt_dedisperse_spectra")
+
+
+def cdmt_dedisperse(plan, workspace, ws_bytes, voltages, nblock, dms, out, stream) -> None:
+    arr, n = _dm_array(dms)
+    _check(load().cdmt_dedisperse(plan, workspace, ws_bytes, voltages, nblock, arr, n, out,
+                                  stream), "cdmt_dedisperse")
+
+
+def cdmt_destroy(plan) -> None:
+    if plan:
+        load().cdmt_destroy(plan)
+
+
+# ------------------------------------------------- torch-facing wrapper ----
+
+class Plan:
+    """Owns a cdmt plan; torch supplies the device memory and the stream."""
+
+    def __init__(self, nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec, *,
+                 input_kind=INPUT_CF32, chirp_ref=CHIRP_CHANNEL, sign=-1, dm_tile=None):
+        self.handle = cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec)
+        self.nsub, self.nfft, self.noverlap, self.nchan, self.ndec = \
+            nsub, nfft, noverlap, nchan, ndec
+        cdmt_plan_set(self.handle, CDMT_OPT_INPUT, input_kind)
+        cdmt_plan_set(self.handle, CDMT_OPT_CHIRP_REF, chirp_ref)
+        cdmt_plan_set(self.handle, CDMT_OPT_SIGN, sign)
+        if dm_tile is not None:
+            cdmt_plan_set(self.handle, CDMT_OPT_DM_TILE, dm_tile)
+        self.input_kind = input_kind
+
+    def __del__(self):
+        try:
+            cdmt_destroy(self.handle)
+        except Exception:
+            pass
+
+    def shape(self, nblock):
+        return cdmt_output_shape(self.handle, nblock)
+
+    def workspace(self, nblock, device="cuda"):
+        import torch
+        n = cdmt_workspace_size(self.handle, nblock)
+        return torch.empty(max(n, 1), dtype=torch.uint8, device=device)
+
+    def _stream(self, stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _check_voltages(self, x, nblock):
+        import torch
+        want = torch.int8 if self.input_kind == INPUT_CI8 else torch.float32
+        ntin, _, _ = self.shape(nblock)
+        if x.dtype != want or not x.is_cuda or not x.is_contiguous():
+            raise ValueError(f"voltages must be a contiguous {want} device tensor")
+        if tuple(x.shape) != (self.nsub, ntin, 2, 2):
+            raise ValueError(f"voltages shape {tuple(x.shape)} != {(self.nsub, ntin, 2, 2)}")
+
+    def dedisperse(self, x, nblock, dms, out=None, workspace=None, stream=None):
+        """Filterbank [ndm][ntime_out][nsub*nchan] float32 for device voltages
+        x [nsub][ntime_in][2][2] (float32 or int8)."""
+        import torch
+        self._check_voltages(x, nblock)
+        _, ntout, nch = self.shape(nblock)
+        if out is None:
+            out = torch.empty((len(dms), ntout, nch), dtype=torch.float32, device=x.device)
+        if workspace is None:
+            workspace = self.workspace(nblock, x.device)
+        cdmt_dedisperse(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                        ctypes.c_void_p(x.data_ptr()), nblock, dms,
+                        ctypes.c_void_p(out.data_ptr()), self._stream(stream))
+        return out
+
+    def forward(self, x, nblock, workspace, stream=None):
+        self._check_voltages(x, nblock)
+        cdmt_forward(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                     ctypes.c_void_p(x.data_ptr()), nblock, self._stream(stream))
+
+    def dedisperse_spectra(self, nblock, dms, out, workspace, stream=None):
+        cdmt_dedisperse_spectra(self.handle, ctypes.c_void_p(workspace.data_ptr()),
+                                workspace.numel(), nblock, dms, ctypes.c_void_p(out.data_ptr()),
+                                self._stream(stream))
+        return out
+
+
+def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
+    """Seconds of data covered by nblock blocks (the metric's data-seconds)."""
+    return nblock * (nfft - noverlap) / (bw_mhz * 1e6)
+
+
+__all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
+                                                          "dm_seconds", "EXPORTS"]

@@ -1,0 +1,643 @@
+// MI355X (gfx950) coherent dedispersion to many DM trials.
+//
+// Method: Bassa, Pleunis & Hessels (2016), Sec. 2-3 and Alg. 1.  For each
+// block of N_bin samples of each subband (blocks overlap by n_d n_c samples):
+// forward FFT, swap halves, then for every DM trial: multiply each channel's
+// bins by the transfer function of Eq. 1, swap halves per channel, backward
+// FFT of M_bin = N_bin / n_c, drop n_d/2 samples at each edge, detect
+// |X|^2 + |Y|^2, sum ndec consecutive samples, and store the filterbank as
+// [DM][time][channel] with channels in decreasing frequency.
+//
+// Kernels (all hand-written here, see fft_core.hpp for the FFT engine):
+//   fwd_col  first pass of a four-step N_bin = N1 x N2 forward FFT: reads the
+//            voltages (int8 or float32, widened exactly), N2-point transforms
+//            over stride-N1 columns, four-step twiddle, stores [k2][n1].
+//   fwd_row  second pass: N1-point transforms over rows, transposed through
+//            LDS so the store is contiguous, swap of halves and the 1/N_bin
+//            normalisation folded into the store; spectra are kept as
+//            [block][subband][bin] pairs (both pols), so channel c of a
+//            subband is the contiguous run of bins [c M, (c+1) M).
+//   fused_dedisperse  one workgroup per (channel chunk(s), DM tile): loads a
+//            channel's M bins once into registers and, for each DM of the
+//            tile, applies the transfer function (phase in FP64, reduced to
+//            [-1/2, 1/2) cycles, then FP32 sincos), runs the M-point backward
+//            FFT in registers + LDS, detects, downsamples and stores.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/cdmt.h"
+#include "fft_core.hpp"
+
+using cdmt::cpair;
+
+namespace {
+
+// Sec. 2, text after Eq. 1: k_DM^{-1} = 2.41e-4 s MHz^2 (per unit DM).
+constexpr double kKdm = 1.0 / 2.41e-4;
+
+constexpr int kMaxDmPerLaunch = 256;
+constexpr int kTwiddleEntries = 1 << 18;   // sizes 1 .. 2^17, table P at [P, 2P)
+
+__device__ float2 g_twiddle[kTwiddleEntries];
+
+__device__ __forceinline__ const float2 *twiddles(int p) { return g_twiddle + p; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+// contiguous range of logical indices so that neighbouring work (the
+// channels of one subband block, consecutive DM tiles) shares an L2.
+__device__ __forceinline__ int xcd_remap(int w, int g) {
+    const int q = g >> 3, r = g & 7;
+    const int xcd = w & 7, i = w >> 3;
+    return (xcd < r) ? xcd * (q + 1) + i : r * (q + 1) + (xcd - r) * q + i;
+}
+
+struct FwdArgs {
+    const void *x;          // voltages [nsub][ntime_in][2][2]
+    cpair *ybuf;            // four-step intermediate [block][subband][k2][n1]
+    cpair *spec;            // spectra [block][subband][N]
+    long long ntime_in;
+    int nsub, nblock, n1, n2, n, step;   // step = N - noverlap
+    float inv_n;
+};
+
+// ---------------------------------------------------------------------------
+// Forward FFT, pass 1 (columns).  P = N2.  C = 4096/P columns per workgroup,
+// lane t -> column f = t % C (fastest, so loads are contiguous in time),
+// tt = t / C.
+template <int P, bool CI8>
+__global__ __launch_bounds__(256) void fwd_col(FwdArgs a) {
+    constexpr int T = P / 16, C = 4096 / P;
+    __shared__ cpair sh[P * C];
+    const int groups = a.n1 / C;
+    const int g = blockIdx.x % groups;
+    const int bs = blockIdx.x / groups;          // block * nsub + subband
+    const int s = bs % a.nsub, b = bs / a.nsub;
+    const int t = threadIdx.x, f = t % C, tt = t / C;
+    const int n1 = g * C + f;
+    const long long first = (long long)s * a.ntime_in + (long long)b * a.step + n1;
+
+    cpair v[16];
+    if constexpr (CI8) {
+        // one dword = one time sample: bytes X.re, X.im, Y.re, Y.im (int8)
+        const int *x = reinterpret_cast<const int *>(a.x) + first;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int w = x[(long long)a.n1 * (tt + T * q)];
+            v[q] = make_float4((float)(int8_t)w, (float)(int8_t)(w >> 8),
+                               (float)(int8_t)(w >> 16), (float)(int8_t)(w >> 24));
+        }
+    } else {
+        const float4 *x = reinterpret_cast<const float4 *>(a.x) + first;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = x[(long long)a.n1 * (tt + T * q)];
+    }
+    cdmt::LdsInterleaved<C> lds{sh + f};
+    cdmt::Stage<P, 1, -1>::run(v, tt, lds, twiddles(P));
+
+    // four-step twiddle exp(-2 pi i n1 k2 / N), then store row k2
+    const float2 *twn = twiddles(a.n);
+    cpair *y = a.ybuf + (long long)bs * a.n;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k2 = tt + T * q;
+        float2 w = twn[(n1 * k2) & (a.n - 1)];
+        w.y = -w.y;
+        y[(long long)k2 * a.n1 + n1] = cdmt::pmul(v[q], w);
+    }
+}
+
+// Forward FFT, pass 2 (rows).  P = N1.  C = 4096/P rows per workgroup.
+template <int P>
+__global__ __launch_bounds__(256) void fwd_row(FwdArgs a) {
+    constexpr int T = P / 16, C = 4096 / P;
+    constexpr int STRIDE = P + P / 16 + 1;    // odd: conflict-free transposed reads
+    __shared__ cpair sh[C * STRIDE];
+    const int groups = a.n2 / C;
+    const int g = blockIdx.x % groups;
+    const int bs = blockIdx.x / groups;
+    const int t = threadIdx.x;
+    const int f = t / T, tt = t % T;          // lanes along the row: contiguous loads
+    const int k2 = g * C + f;
+
+    const cpair *y = a.ybuf + (long long)bs * a.n + (long long)k2 * P;
+    cpair v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        v[q] = y[tt + T * q];
+    cdmt::LdsPadded lds{sh + f * STRIDE};
+    cdmt::Stage<P, 1, -1>::run(v, tt, lds, twiddles(P));
+
+    // X[k2 + N2 k1] with k1 = tt + T q.  Transpose through LDS so that
+    // consecutive lanes store consecutive k2, i.e. consecutive bins.
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        lds.store(tt + T * q, v[q]);
+    __syncthreads();
+    const int f2 = t % C, tt2 = t / C;
+    const cdmt::LdsPadded rd{sh + f2 * STRIDE};
+    cpair *spec = a.spec + (long long)bs * a.n;
+    const int half = a.n >> 1;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k1 = tt2 + T * q;
+        const int k = g * C + f2 + a.n2 * k1;
+        const int j = (k + half) & (a.n - 1);     // swap halves per subband
+        spec[j] = cdmt::pscale(rd.load(k1), a.inv_n);
+    }
+}
+
+struct FusedArgs {
+    const cpair *spec;      // [block][subband][N]
+    float *out;             // first DM of this launch: [ndm][ntime_out][nsub*nchan]
+    long long ntime_out;
+    int nsub, nchan, n, nchunks, ndm, dm_tile;
+    int nd_half, ndec, tblk, nch_out;
+    int inner, ndt;         // chunk groups per subband block; DM tiles
+    int chirp_ref;
+    float sign;
+    double f_centre, bw, delta, kk;   // MHz, MHz, bw/N MHz, 1e6 k_DM
+};
+
+struct DmList {
+    double dm[kMaxDmPerLaunch];
+};
+
+// Transfer function, FFT, detection and downsampling for C = WG/T channel
+// chunks of M bins and a tile of DMs.
+template <int M>
+__global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedArgs a,
+                                                                          DmList dl) {
+    constexpr int WG = M >= 8192 ? 512 : 256;
+    constexpr int T = M / 16;
+    constexpr int C = WG / T;
+    constexpr int STRIDE = M + M / 16 + 1;
+    __shared__ cpair sh[C * STRIDE];
+
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int ci = lw % a.inner;
+    const int rest = lw / a.inner;
+    const int dt = rest % a.ndt;
+    const int cg = (rest / a.ndt) * a.inner + ci;
+
+    const int t = threadIdx.x;
+    const int f = t / T, tt = t % T;
+    const int chunk = cg * C + f;
+    const bool valid = chunk < a.nchunks;
+    const int cc = valid ? chunk : 0;
+    const int c = cc % a.nchan;
+    const int bs = cc / a.nchan;
+    const int s = bs % a.nsub;
+    const int b = bs / a.nsub;
+
+    // this channel's M bins, both pols, increasing frequency
+    cpair raw[16];
+    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        raw[q] = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+
+    // DM-independent part of Eq. 1 per bin, in cycles per unit DM:
+    //   1e6 k_DM nu^2 / (nu0^2 (nu0 + nu)),  nu = offset from nu0 (MHz)
+    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
+    double nu0, off;
+    if (a.chirp_ref == 0) {
+        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
+        off = -0.5 * M;
+    } else {
+        nu0 = fs;
+        off = (double)c * M - 0.5 * a.n;
+    }
+    const double scale = a.kk / (nu0 * nu0);
+    double g[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const double nu = ((double)(tt + T * q) + off) * a.delta;
+        g[q] = scale * nu * nu / (nu0 + nu);
+    }
+
+    const cdmt::LdsPadded lds{sh + f * STRIDE};
+    float *inten = reinterpret_cast<float *>(sh + f * STRIDE);
+    const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
+    const int d0 = dt * a.dm_tile;
+    const int d1 = min(a.ndm, d0 + a.dm_tile);
+
+    for (int d = d0; d < d1; ++d) {
+        const double dm = dl.dm[d];
+        cpair v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double ph = dm * g[q];
+            const float u = (float)(ph - rint(ph));    // cycles in [-1/2, 1/2]
+            float sn, cs;
+            sincospif(2.0f * u, &sn, &cs);
+            // swap halves per channel: bin i -> transform input (i + M/2) mod M
+            v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, a.sign * sn));
+        }
+        cdmt::Stage<M, 1, +1>::run(v, tt, lds, twiddles(M));
+
+        // detect; channel sample m = tt + T q
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const cpair y = v[q];
+            inten[tt + T * q] = y.x * y.x + y.y * y.y + y.z * y.z + y.w * y.w;
+        }
+        __syncthreads();
+        if (valid) {
+            float *o = a.out + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + col;
+            for (int tq = tt; tq < a.tblk; tq += T) {
+                const float *p = inten + a.nd_half + tq * a.ndec;
+                float acc = 0.f;
+                for (int q = 0; q < a.ndec; ++q)
+                    acc += p[q];
+                o[(long long)tq * a.nch_out] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+std::mutex g_init_mu;
+std::vector<char> g_init_done;   // per device
+
+int ensure_twiddles() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return CDMT_E_DEVICE;
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if ((int)g_init_done.size() <= dev)
+        g_init_done.resize(dev + 1, 0);
+    if (g_init_done[dev])
+        return CDMT_OK;
+    std::vector<float2> h(kTwiddleEntries);
+    h[0] = make_float2(1.f, 0.f);
+    for (int p = 1; p < kTwiddleEntries; p <<= 1) {
+        for (int n = 0; n < p; ++n) {
+            // exp(+2 pi i n / p); the angle is formed from the exact fraction
+            const double a = 2.0 * M_PI * ((double)n / (double)p);
+            h[p + n] = make_float2((float)std::cos(a), (float)std::sin(a));
+        }
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), h.data(), sizeof(float2) * h.size()) !=
+        hipSuccess)
+        return CDMT_E_DEVICE;
+    g_init_done[dev] = 1;
+    return CDMT_OK;
+}
+
+bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
+int ilog2(long long v) {
+    int l = 0;
+    while ((1LL << l) < v)
+        ++l;
+    return l;
+}
+
+}  // namespace
+
+struct cdmt_plan_s {
+    int nsub, nfft, noverlap, nchan, ndec;
+    double f_centre, bw;
+    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 4;
+    int m, nd, tblk, n1, n2;
+};
+
+namespace {
+
+template <int P>
+void launch_col(const FwdArgs &a, int ci8, int grid, hipStream_t st) {
+    if (ci8)
+        fwd_col<P, true><<<grid, 256, 0, st>>>(a);
+    else
+        fwd_col<P, false><<<grid, 256, 0, st>>>(a);
+}
+
+int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hipStream_t st) {
+    const long long nspec = (long long)nblock * p->nsub * p->nfft;
+    FwdArgs a;
+    a.x = x;
+    a.spec = reinterpret_cast<cpair *>(ws);
+    a.ybuf = a.spec + nspec;
+    a.ntime_in = (long long)nblock * (p->nfft - p->noverlap) + p->noverlap;
+    a.nsub = p->nsub;
+    a.nblock = nblock;
+    a.n1 = p->n1;
+    a.n2 = p->n2;
+    a.n = p->nfft;
+    a.step = p->nfft - p->noverlap;
+    a.inv_n = 1.0f / (float)p->nfft;
+
+    const long long bsn = (long long)nblock * p->nsub;
+    const long long gcol = bsn * (p->n1 / (4096 / p->n2));
+    const long long grow = bsn * (p->n2 / (4096 / p->n1));
+    if (gcol > 0x7fffffffLL || grow > 0x7fffffffLL)
+        return CDMT_E_SHAPE;
+    switch (p->n2) {
+    case 64: launch_col<64>(a, p->input_kind, (int)gcol, st); break;
+    case 128: launch_col<128>(a, p->input_kind, (int)gcol, st); break;
+    case 256: launch_col<256>(a, p->input_kind, (int)gcol, st); break;
+    default: return CDMT_E_UNSUPPORTED;
+    }
+    switch (p->n1) {
+    case 64: fwd_row<64><<<(int)grow, 256, 0, st>>>(a); break;
+    case 128: fwd_row<128><<<(int)grow, 256, 0, st>>>(a); break;
+    case 256: fwd_row<256><<<(int)grow, 256, 0, st>>>(a); break;
+    case 512: fwd_row<512><<<(int)grow, 256, 0, st>>>(a); break;
+    default: return CDMT_E_UNSUPPORTED;
+    }
+    return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
+}
+
+template <int M>
+int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t st) {
+    constexpr int WG = M >= 8192 ? 512 : 256;
+    constexpr int C = WG / (M / 16);
+    for (int first = 0; first < ndm; first += kMaxDmPerLaunch) {
+        FusedArgs a = a0;
+        const int cnt = ndm - first < kMaxDmPerLaunch ? ndm - first : kMaxDmPerLaunch;
+        DmList dl;
+        std::memset(&dl, 0, sizeof(dl));
+        for (int i = 0; i < cnt; ++i)
+            dl.dm[i] = dms[first + i];
+        a.ndm = cnt;
+        a.out = a0.out + (long long)first * a0.ntime_out * a0.nch_out;
+        const long long ncg = (a.nchunks + C - 1) / C;
+        a.inner = a.nchan >= C ? a.nchan / C : 1;
+        a.ndt = (cnt + a.dm_tile - 1) / a.dm_tile;
+        const long long grid = ncg * a.ndt;
+        if (grid > 0x7fffffffLL)
+            return CDMT_E_SHAPE;
+        fused_dedisperse<M><<<(int)grid, WG, 0, st>>>(a, dl);
+        if (hipGetLastError() != hipSuccess)
+            return CDMT_E_DEVICE;
+    }
+    return CDMT_OK;
+}
+
+int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *dms, int ndm,
+                      float *out, hipStream_t st) {
+    FusedArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.spec = reinterpret_cast<const cpair *>(ws);
+    a.out = out;
+    a.ntime_out = (long long)nblock * p->tblk;
+    a.nsub = p->nsub;
+    a.nchan = p->nchan;
+    a.n = p->nfft;
+    a.nchunks = nblock * p->nsub * p->nchan;
+    a.dm_tile = p->dm_tile;
+    a.nd_half = p->nd / 2;
+    a.ndec = p->ndec;
+    a.tblk = p->tblk;
+    a.nch_out = p->nsub * p->nchan;
+    a.chirp_ref = p->chirp_ref;
+    a.sign = (float)p->sign;
+    a.f_centre = p->f_centre;
+    a.bw = p->bw;
+    a.delta = p->bw / p->nfft;
+    a.kk = 1e6 * kKdm;
+    switch (p->m) {
+    case 64: return launch_fused_m<64>(a, dms, ndm, st);
+    case 128: return launch_fused_m<128>(a, dms, ndm, st);
+    case 256: return launch_fused_m<256>(a, dms, ndm, st);
+    case 512: return launch_fused_m<512>(a, dms, ndm, st);
+    case 1024: return launch_fused_m<1024>(a, dms, ndm, st);
+    case 2048: return launch_fused_m<2048>(a, dms, ndm, st);
+    case 4096: return launch_fused_m<4096>(a, dms, ndm, st);
+    case 8192: return launch_fused_m<8192>(a, dms, ndm, st);
+    default: return CDMT_E_UNSUPPORTED;
+    }
+}
+
+int check_plan(const cdmt_plan_s *p) { return p ? CDMT_OK : CDMT_E_ARG; }
+
+int workspace_bytes(const cdmt_plan_s *p, int nblock, size_t *bytes) {
+    if (nblock < 0)
+        return CDMT_E_ARG;
+    const unsigned long long n = (unsigned long long)nblock * p->nsub * p->nfft;
+    *bytes = (size_t)(2ULL * n * sizeof(cpair));
+    return CDMT_OK;
+}
+
+int check_call(const cdmt_plan_s *p, void *ws, size_t ws_bytes, int nblock) {
+    if (!p)
+        return CDMT_E_ARG;
+    if (nblock < 0)
+        return CDMT_E_ARG;
+    size_t need = 0;
+    workspace_bytes(p, nblock, &need);
+    if (nblock > 0 && (!ws || ws_bytes < need))
+        return ws ? CDMT_E_WORKSPACE : CDMT_E_ARG;
+    const long long chunks = (long long)nblock * p->nsub * p->nchan;
+    if (chunks > 0x7fffffffLL)
+        return CDMT_E_SHAPE;
+    return CDMT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdmt_plan(cdmt_plan_t *out, int nsub, double f_centre_mhz, double bw_sub_mhz, int nfft,
+              int noverlap, int nchan, int ndec) {
+    if (!out)
+        return CDMT_E_ARG;
+    *out = nullptr;
+    if (!std::isfinite(f_centre_mhz) || !std::isfinite(bw_sub_mhz))
+        return CDMT_E_ARG;
+    if (nsub < 1 || !is_pow2(nfft) || nfft < 2 || !is_pow2(nchan) || nfft % nchan)
+        return CDMT_E_SHAPE;
+    if (noverlap < 0 || noverlap >= nfft || noverlap % (2 * nchan))
+        return CDMT_E_SHAPE;
+    const int m = nfft / nchan, nd = noverlap / nchan;
+    if (ndec < 1 || (m - nd) % ndec)
+        return CDMT_E_SHAPE;
+    if (!(bw_sub_mhz > 0) || !(f_centre_mhz - nsub * bw_sub_mhz / 2 > 0))
+        return CDMT_E_SHAPE;
+    if (nfft < 4096 || nfft > (1 << 17) || m < 64 || m > 8192)
+        return CDMT_E_UNSUPPORTED;
+    cdmt_plan_s *p = new (std::nothrow) cdmt_plan_s;
+    if (!p)
+        return CDMT_E_ARG;
+    p->nsub = nsub;
+    p->nfft = nfft;
+    p->noverlap = noverlap;
+    p->nchan = nchan;
+    p->ndec = ndec;
+    p->f_centre = f_centre_mhz;
+    p->bw = bw_sub_mhz;
+    p->m = m;
+    p->nd = nd;
+    p->tblk = (m - nd) / ndec;
+    const int l = ilog2(nfft);
+    p->n2 = 1 << (l / 2);
+    p->n1 = nfft / p->n2;
+    *out = p;
+    return CDMT_OK;
+}
+
+int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
+    if (!p)
+        return CDMT_E_ARG;
+    switch (opt) {
+    case CDMT_OPT_INPUT:
+        if (value != 0 && value != 1)
+            return CDMT_E_ARG;
+        p->input_kind = value;
+        return CDMT_OK;
+    case CDMT_OPT_CHIRP_REF:
+        if (value != 0 && value != 1)
+            return CDMT_E_ARG;
+        p->chirp_ref = value;
+        return CDMT_OK;
+    case CDMT_OPT_SIGN:
+        if (value != 1 && value != -1)
+            return CDMT_E_ARG;
+        p->sign = value;
+        return CDMT_OK;
+    case CDMT_OPT_PRECISION:
+        if (value < 0 || value > 2)
+            return CDMT_E_ARG;
+        if (value != 0)
+            return CDMT_E_UNSUPPORTED;
+        p->precision = value;
+        return CDMT_OK;
+    case CDMT_OPT_DM_TILE:
+        if (value < 1 || value > 16)
+            return CDMT_E_ARG;
+        p->dm_tile = value;
+        return CDMT_OK;
+    default:
+        return CDMT_E_ARG;
+    }
+}
+
+int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
+    if (!p || !value)
+        return CDMT_E_ARG;
+    switch (opt) {
+    case CDMT_OPT_INPUT: *value = p->input_kind; return CDMT_OK;
+    case CDMT_OPT_CHIRP_REF: *value = p->chirp_ref; return CDMT_OK;
+    case CDMT_OPT_SIGN: *value = p->sign; return CDMT_OK;
+    case CDMT_OPT_PRECISION: *value = p->precision; return CDMT_OK;
+    case CDMT_OPT_DM_TILE: *value = p->dm_tile; return CDMT_OK;
+    default: return CDMT_E_ARG;
+    }
+}
+
+int cdmt_noverlap_for(double f_lo_mhz, double bw_sub_mhz, double dm_max, int nchan, int ndec,
+                      int chirp_ref, int *noverlap_out) {
+    if (!noverlap_out || !std::isfinite(f_lo_mhz) || !std::isfinite(bw_sub_mhz) ||
+        !std::isfinite(dm_max))
+        return CDMT_E_ARG;
+    if (!(f_lo_mhz > 0) || !(bw_sub_mhz > 0) || dm_max < 0 || !is_pow2(nchan) || ndec < 1 ||
+        (chirp_ref != 0 && chirp_ref != 1))
+        return CDMT_E_ARG;
+    // Eq. 2 over the lowest channel (or the lowest subband), then
+    // n_d n_c = r t_d subband samples (Sec. 2), r = bw in samples/s
+    const double hi = f_lo_mhz + (chirp_ref == 0 ? bw_sub_mhz / nchan : bw_sub_mhz);
+    const double td = kKdm * (1.0 / (f_lo_mhz * f_lo_mhz) - 1.0 / (hi * hi)) * dm_max;
+    const double need = std::ceil(bw_sub_mhz * 1e6 * td - 1e-9);
+    const long long unit = 2LL * nchan * ndec;
+    const long long nov = ((long long)need + unit - 1) / unit * unit;
+    if (nov > 0x7fffffffLL)
+        return CDMT_E_SHAPE;
+    *noverlap_out = (int)nov;
+    return CDMT_OK;
+}
+
+int cdmt_output_shape(cdmt_plan_t p, int nblock, long long *ntime_in, long long *ntime_out,
+                      int *nchan_out) {
+    if (check_plan(p) || nblock < 0)
+        return CDMT_E_ARG;
+    if (ntime_in)
+        *ntime_in = (long long)nblock * (p->nfft - p->noverlap) + p->noverlap;
+    if (ntime_out)
+        *ntime_out = (long long)nblock * p->tblk;
+    if (nchan_out)
+        *nchan_out = p->nsub * p->nchan;
+    return CDMT_OK;
+}
+
+int cdmt_workspace_size(cdmt_plan_t p, int nblock, size_t *bytes) {
+    if (check_plan(p) || !bytes)
+        return CDMT_E_ARG;
+    return workspace_bytes(p, nblock, bytes);
+}
+
+int cdmt_forward(cdmt_plan_t p, void *ws, size_t ws_bytes, const void *voltages, int nblock,
+                 void *hip_stream) {
+    int st = check_call(p, ws, ws_bytes, nblock);
+    if (st)
+        return st;
+    if (nblock == 0)
+        return CDMT_OK;
+    if (!voltages)
+        return CDMT_E_ARG;
+    if ((st = ensure_twiddles()))
+        return st;
+    return launch_forward(p, ws, voltages, nblock, (hipStream_t)hip_stream);
+}
+
+int cdmt_dedisperse_spectra(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock,
+                            const double *dm_list, int ndm, float *out, void *hip_stream) {
+    int st = check_call(p, ws, ws_bytes, nblock);
+    if (st)
+        return st;
+    if (ndm < 0)
+        return CDMT_E_ARG;
+    if (ndm == 0 || nblock == 0)
+        return CDMT_OK;
+    if (!dm_list || !out)
+        return CDMT_E_ARG;
+    for (int i = 0; i < ndm; ++i)
+        if (!std::isfinite(dm_list[i]))
+            return CDMT_E_ARG;
+    if ((st = ensure_twiddles()))
+        return st;
+    return launch_dedisperse(p, ws, nblock, dm_list, ndm, out, (hipStream_t)hip_stream);
+}
+
+int cdmt_dedisperse(cdmt_plan_t p, void *ws, size_t ws_bytes, const void *voltages, int nblock,
+                    const double *dm_list, int ndm, float *out, void *hip_stream) {
+    int st = check_call(p, ws, ws_bytes, nblock);
+    if (st)
+        return st;
+    if (ndm < 0)
+        return CDMT_E_ARG;
+    if (ndm == 0 || nblock == 0)
+        return CDMT_OK;
+    if (!voltages || !dm_list || !out)
+        return CDMT_E_ARG;
+    for (int i = 0; i < ndm; ++i)
+        if (!std::isfinite(dm_list[i]))
+            return CDMT_E_ARG;
+    if ((st = cdmt_forward(p, ws, ws_bytes, voltages, nblock, hip_stream)))
+        return st;
+    return cdmt_dedisperse_spectra(p, ws, ws_bytes, nblock, dm_list, ndm, out, hip_stream);
+}
+
+void cdmt_destroy(cdmt_plan_t p) { delete p; }
+
+const char *cdmt_status_string(int status) {
+    switch (status) {
+    case CDMT_OK: return "ok";
+    case CDMT_E_ARG: return "invalid argument";
+    case CDMT_E_SHAPE: return "shape violates the method's constraints";
+    case CDMT_E_WORKSPACE: return "workspace too small";
+    case CDMT_E_DEVICE: return "HIP device error";
+    case CDMT_E_UNSUPPORTED: return "configuration not supported by this build";
+    default: return "unknown status";
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+// Workgroup-level complex FFT building blocks for gfx950.
+//
+// Data type: a "pair" (float4) holds the same sample or bin of both
+// polarisations, (X.re, X.im, Y.re, Y.im); every butterfly works on both at
+// once, so one twiddle or transfer-function factor serves two complex values.
+//
+// Transform layout: a P-point transform (P a power of two, 32 <= P <= 8192)
+// is spread over T = P/16 lanes; lane tt holds elements tt + T*slot in
+// registers v[slot], slot = 0..15, at the input and at the output (natural
+// order both ways).  Stages are Stockham autosort, decimation in time:
+// radix 16 while at least 16 elements remain, then one radix 2/4/8 stage.
+// Between stages the values go through LDS once (write in the stage's output
+// order, read back in the next stage's input order); the first stage reads
+// registers and the last leaves its outputs in registers.
+//
+// Twiddles come from a table of exp(+2 pi i n / P), n in [0, P), held per
+// transform size in device memory and computed on the host in double
+// precision (the forward sign conjugates on the fly).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace cdmt {
+
+typedef float4 cpair;
+
+__device__ __forceinline__ cpair padd(cpair a, cpair b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ cpair psub(cpair a, cpair b) {
+    return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+// both complex values times the complex number w
+__device__ __forceinline__ cpair pmul(cpair a, float2 w) {
+    return make_float4(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x,
+                       a.z * w.x - a.w * w.y, a.z * w.y + a.w * w.x);
+}
+__device__ __forceinline__ cpair pscale(cpair a, float s) {
+    return make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
+}
+// both complex values times S*i (S = +1 or -1)
+template <int S>
+__device__ __forceinline__ cpair pmuli(cpair a) {
+    if constexpr (S > 0)
+        return make_float4(-a.y, a.x, -a.w, a.z);
+    else
+        return make_float4(a.y, -a.x, a.w, -a.z);
+}
+
+// cos and sin of 2 pi e / 16
+__device__ __forceinline__ constexpr float c16(int e) {
+    constexpr float t[16] = {1.0f, 0.92387953251128674f, 0.70710678118654752f,
+                             0.38268343236508977f, 0.0f, -0.38268343236508977f,
+                             -0.70710678118654752f, -0.92387953251128674f, -1.0f,
+                             -0.92387953251128674f, -0.70710678118654752f,
+                             -0.38268343236508977f, 0.0f, 0.38268343236508977f,
+                             0.70710678118654752f, 0.92387953251128674f};
+    return t[e & 15];
+}
+__device__ __forceinline__ constexpr float s16(int e) { return c16(e + 12); }
+
+// times exp(S 2 pi i E / 16), with the trivial and 1/sqrt(2) cases special-cased
+template <int S, int E>
+__device__ __forceinline__ cpair pmul16(cpair a) {
+    constexpr int e = E & 15;
+    if constexpr (e == 0) {
+        return a;
+    } else if constexpr (e == 4) {
+        return pmuli<S>(a);
+    } else if constexpr (e == 8) {
+        return make_float4(-a.x, -a.y, -a.z, -a.w);
+    } else if constexpr (e == 12) {
+        return pmuli<-S>(a);
+    } else if constexpr ((e & 3) == 2) {
+        // (c + i S s) with |c| = |s| = 1/sqrt(2)
+        constexpr float h = 0.70710678118654752f;
+        constexpr float cr = (e == 2 || e == 14) ? h : -h;
+        constexpr float ci = (e == 2 || e == 6) ? (S > 0 ? h : -h) : (S > 0 ? -h : h);
+        // (a + ib)(cr + i ci) with |cr| = |ci|
+        if constexpr (cr == ci) {
+            return make_float4(cr * (a.x - a.y), cr * (a.x + a.y), cr * (a.z - a.w),
+                               cr * (a.z + a.w));
+        } else {
+            return make_float4(cr * (a.x + a.y), cr * (a.y - a.x), cr * (a.z + a.w),
+                               cr * (a.w - a.z));
+        }
+    } else {
+        constexpr float cr = c16(e);
+        constexpr float ci = S > 0 ? s16(e) : -s16(e);
+        return make_float4(a.x * cr - a.y * ci, a.x * ci + a.y * cr, a.z * cr - a.w * ci,
+                           a.z * ci + a.w * cr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers: y[k] = sum_n a[n] exp(S 2 pi i n k / r), natural
+// order in and out.
+
+template <int S>
+__device__ __forceinline__ void dft2(cpair *a) {
+    cpair t = a[0];
+    a[0] = padd(t, a[1]);
+    a[1] = psub(t, a[1]);
+}
+
+template <int S>
+__device__ __forceinline__ void dft4(cpair &a0, cpair &a1, cpair &a2, cpair &a3) {
+    cpair s02 = padd(a0, a2), d02 = psub(a0, a2);
+    cpair s13 = padd(a1, a3), d13 = pmuli<S>(psub(a1, a3));
+    a0 = padd(s02, s13);
+    a2 = psub(s02, s13);
+    a1 = padd(d02, d13);
+    a3 = psub(d02, d13);
+}
+
+template <int S>
+__device__ __forceinline__ void dft4(cpair *a) { dft4<S>(a[0], a[1], a[2], a[3]); }
+
+template <int S>
+__device__ __forceinline__ void dft8(cpair *a) {
+    // even / odd split: y[k] = E[k] + w8^k O[k], y[k+4] = E[k] - w8^k O[k]
+    cpair e[4] = {a[0], a[2], a[4], a[6]};
+    cpair o[4] = {a[1], a[3], a[5], a[7]};
+    dft4<S>(e);
+    dft4<S>(o);
+    o[1] = pmul16<S, 2>(o[1]);
+    o[2] = pmul16<S, 4>(o[2]);
+    o[3] = pmul16<S, 6>(o[3]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = padd(e[k], o[k]);
+        a[k + 4] = psub(e[k], o[k]);
+    }
+}
+
+template <int S>
+__device__ __forceinline__ void dft16(cpair *a) {
+    // n = 4m + e: four DFT-4 over m, twiddle w16^(e k'), four DFT-4 over e.
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        dft4<S>(a[e], a[e + 4], a[e + 8], a[e + 12]);
+    a[5] = pmul16<S, 1>(a[5]);
+    a[6] = pmul16<S, 2>(a[6]);
+    a[7] = pmul16<S, 3>(a[7]);
+    a[9] = pmul16<S, 2>(a[9]);
+    a[10] = pmul16<S, 4>(a[10]);
+    a[11] = pmul16<S, 6>(a[11]);
+    a[13] = pmul16<S, 3>(a[13]);
+    a[14] = pmul16<S, 6>(a[14]);
+    a[15] = pmul16<S, 9>(a[15]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        dft4<S>(a[4 * k], a[4 * k + 1], a[4 * k + 2], a[4 * k + 3]);
+    // y[k] sits at a[4 (k mod 4) + k / 4]: transpose the 4x4 block
+    cpair y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        y[k] = a[4 * (k & 3) + (k >> 2)];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        a[k] = y[k];
+}
+
+template <int R, int S>
+__device__ __forceinline__ void dft(cpair *a) {
+    if constexpr (R == 16)
+        dft16<S>(a);
+    else if constexpr (R == 8)
+        dft8<S>(a);
+    else if constexpr (R == 4)
+        dft4<S>(a);
+    else if constexpr (R == 2)
+        dft2<S>(a);
+}
+
+// ---------------------------------------------------------------------------
+// LDS views of one transform's elements.
+
+// element e at base[e + e/16]: one padding slot per 16 elements keeps the
+// stride-16 writes of the first stage off a single bank group
+struct LdsPadded {
+    cpair *base;
+    __device__ __forceinline__ void store(int e, cpair v) const { base[e + (e >> 4)] = v; }
+    __device__ __forceinline__ cpair load(int e) const { return base[e + (e >> 4)]; }
+};
+
+// element e of transform f at base[e*C + f]: several transforms interleaved,
+// consecutive lanes (consecutive f) touch consecutive addresses
+template <int C>
+struct LdsInterleaved {
+    cpair *base;  // already offset by f
+    __device__ __forceinline__ void store(int e, cpair v) const { base[e * C] = v; }
+    __device__ __forceinline__ cpair load(int e) const { return base[e * C]; }
+};
+
+// ---------------------------------------------------------------------------
+// One Stockham stage (and, recursively, the rest) of a P-point transform with
+// sign S.  NS = product of the radices already applied.
+template <int P, int NS, int S>
+struct Stage {
+    static constexpr int R = 16;
+    static constexpr int T = P / R;
+    static constexpr int r = (P / NS >= R) ? R : P / NS;
+    static constexpr int U = R / r;          // butterflies per lane
+    static constexpr bool LAST = (NS * r == P);
+
+    template <class Lds>
+    __device__ __forceinline__ static void run(cpair (&v)[16], int tt, const Lds &lds,
+                                               const float2 *__restrict__ tw) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int j = tt + T * u;
+            const int k = j & (NS - 1);
+            cpair a[r];
+#pragma unroll
+            for (int q = 0; q < r; ++q)
+                a[q] = v[u + q * U];
+            if constexpr (NS > 1) {
+#pragma unroll
+                for (int q = 1; q < r; ++q) {
+                    float2 w = tw[k * q * (P / (NS * r))];
+                    if constexpr (S < 0)
+                        w.y = -w.y;
+                    a[q] = pmul(a[q], w);
+                }
+            }
+            dft<r, S>(a);
+            if constexpr (LAST) {
+#pragma unroll
+                for (int q = 0; q < r; ++q)
+                    v[u + q * U] = a[q];
+            } else {
+                const int base = (j / NS) * NS * r + k;
+#pragma unroll
+                for (int q = 0; q < r; ++q)
+                    lds.store(base + q * NS, a[q]);
+            }
+        }
+        if constexpr (!LAST) {
+            __syncthreads();
+#pragma unroll
+            for (int s = 0; s < R; ++s)
+                v[s] = lds.load(tt + T * s);
+            __syncthreads();
+            Stage<P, NS * r, S>::run(v, tt, lds, tw);
+        }
+    }
+};
+
+}  // namespace cdmt

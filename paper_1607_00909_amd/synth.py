@@ -140,19 +140,24 @@ def pulse_draws(w: Workload, seed: int | None = None):
     return out
 
 
-def device_ci8_noise(nsub: int, ntime: int, sigma: float, seed: int, device):
-    """Large ci8 noise generated directly in device memory with torch's
-    seeded generator (for workloads too big to build on the host).  Returns a
-    torch int8 tensor [nsub][ntime][2][2]; rounding half to even and clipping
-    as encode_ci8."""
+def device_noise(kind: str, nsub: int, ntime: int, sigma: float, seed: int, device):
+    """Large noise generated directly in device memory with torch's seeded
+    generator (for workloads too big to build on the host): a torch tensor
+    [nsub][ntime][2][2], int8 ("ci8": rounded half to even and clipped as
+    encode_ci8) or float32 ("cf32")."""
     import torch
     gen = torch.Generator(device=device)
     gen.manual_seed(int(seed))
-    out = torch.empty((nsub, ntime, 2, 2), dtype=torch.int8, device=device)
+    dt = torch.int8 if kind == "ci8" else torch.float32
+    out = torch.empty((nsub, ntime, 2, 2), dtype=dt, device=device)
     rows = max(1, (1 << 26) // (ntime * 4))
     for s0 in range(0, nsub, rows):
         s1 = min(nsub, s0 + rows)
         z = torch.randn((s1 - s0, ntime, 2, 2), generator=gen, device=device, dtype=torch.float32)
-        out[s0:s1] = torch.clamp(torch.round(z * sigma), -127, 127).to(torch.int8)
+        z *= sigma
+        if kind == "ci8":
+            out[s0:s1] = torch.clamp(torch.round(z), -127, 127).to(torch.int8)
+        else:
+            out[s0:s1] = z
         del z
     return out
