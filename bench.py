@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--chirp-ref", choices=["channel", "subband"], default="channel")
     ap.add_argument("--cpu-pairs", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (counter calibration for profiles)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -131,6 +133,14 @@ def main():
         plan.dedisperse_spectra(w.nblock, dms, out, ws)
         if ev is not None:
             ev[2].record(stream)
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 1 GiB read, 1 GiB written")
+        del src, dst
 
     for i in range(args.warmup):
         step()

@@ -45,7 +45,7 @@ enum cdmt_opt {
     CDMT_OPT_CHIRP_REF = 1,  /* 0: nu0 = channel centre (default), 1: subband centre    */
     CDMT_OPT_SIGN = 2,       /* -1: dedisperse (default), +1: multiply by Eq. 1 as is   */
     CDMT_OPT_PRECISION = 3,  /* 0: FP32 (default); others: CDMT_E_UNSUPPORTED for now    */
-    CDMT_OPT_DM_TILE = 4     /* DM trials per workgroup pass, 1..16 (default 4)         */
+    CDMT_OPT_DM_TILE = 4     /* DM trials per workgroup pass, 1..16 (default 8)         */
 };
 
 /*
@@ -56,11 +56,13 @@ enum cdmt_opt {
  * is centred on f_centre + (s - (n_s-1)/2) * bw.
  *
  *   nsub       n_s >= 1
- *   nfft       N_bin, power of two in [2^10, 2^17]
+ *   nfft       N_bin, power of two in [2^12, 2^17] (other powers of two:
+ *              CDMT_E_UNSUPPORTED)
  *   noverlap   n_d * n_c subband samples; multiple of 2*nchan, < nfft
  *              (Sec. 2: sections overlap by n_d n_c samples, n_d/2 channel
  *              samples discarded at each edge)
  *   nchan      n_c, power of two with M_bin = nfft/nchan in [64, 8192]
+ *              (outside that range: CDMT_E_UNSUPPORTED)
  *   ndec       output samples summed per filterbank sample, >= 1, must
  *              divide M_bin - n_d
  * Requires bw_sub_mhz > 0 and f_centre - nsub*bw/2 > 0.
@@ -117,7 +119,10 @@ int cdmt_forward(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const void 
  * backward FFT of M_bin, unpadding (n_d/2 per edge), detection
  * |X|^2 + |Y|^2, the sum of ndec consecutive samples, and the transpose to
  * [time][channel] with channels in decreasing frequency.
- *   dm_list   host, ndm values in pc cm^-3 (finite; read during the call only)
+ *   dm_list   host, ndm values in pc cm^-3, read during the call only; each
+ *             must be finite with |DM| small enough that the largest phase of
+ *             Eq. 1 over the plan stays below 2^29 cycles (CDMT_E_ARG
+ *             otherwise; the bound is ~1e7 pc cm^-3 at LOFAR frequencies)
  *   out       device float32 [ndm][ntime_out][nsub*nchan]
  * ndm = 0 is a no-op.
  */

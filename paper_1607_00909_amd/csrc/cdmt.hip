@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void fwd_col(FwdArgs a) {
             v[q] = x[(long long)a.n1 * (tt + T * q)];
     }
     cdmt::LdsInterleaved<C> lds{sh + f};
-    cdmt::Stage<P, 1, -1>::run(v, tt, lds, twiddles(P));
+    cdmt::wg_fft<P, -1>(v, tt, lds);
 
     // four-step twiddle exp(-2 pi i n1 k2 / N), then store row k2
     const float2 *twn = twiddles(a.n);
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(256) void fwd_row(FwdArgs a) {
     for (int q = 0; q < 16; ++q)
         v[q] = y[tt + T * q];
     cdmt::LdsPadded lds{sh + f * STRIDE};
-    cdmt::Stage<P, 1, -1>::run(v, tt, lds, twiddles(P));
+    cdmt::wg_fft<P, -1>(v, tt, lds);
 
     // X[k2 + N2 k1] with k1 = tt + T q.  Transpose through LDS so that
     // consecutive lanes store consecutive k2, i.e. consecutive bins.
@@ -153,6 +153,26 @@ __global__ __launch_bounds__(256) void fwd_row(FwdArgs a) {
     }
 }
 
+// sin(pi r) and cos(pi r) for |r| <= 1/2.  Odd / even polynomials whose
+// coefficients were fitted for this kernel by iteratively reweighted least
+// squares toward the minimax error (Lawson's method) on Chebyshev nodes; the
+// largest absolute error in FP32 evaluation is 2.1e-7.
+__device__ __forceinline__ void sincos_pi(float r, float &s, float &c) {
+    const float r2 = r * r;
+    float ps = 7.722071558e-02f;
+    ps = fmaf(ps, r2, -5.980455279e-01f);
+    ps = fmaf(ps, r2, 2.550031424e+00f);
+    ps = fmaf(ps, r2, -5.167706966e+00f);
+    ps = fmaf(ps, r2, 3.141592503e+00f);
+    s = ps * r;
+    float pc = -2.439684793e-02f;
+    pc = fmaf(pc, r2, 2.349376380e-01f);
+    pc = fmaf(pc, r2, -1.335212111e+00f);
+    pc = fmaf(pc, r2, 4.058709145e+00f);
+    pc = fmaf(pc, r2, -4.934802055e+00f);
+    c = fmaf(pc, r2, 1.0f);
+}
+
 struct FusedArgs {
     const cpair *spec;      // [block][subband][N]
     float *out;             // first DM of this launch: [ndm][ntime_out][nsub*nchan]
@@ -160,6 +180,7 @@ struct FusedArgs {
     int nsub, nchan, n, nchunks, ndm, dm_tile;
     int nd_half, ndec, tblk, nch_out;
     int inner, ndt;         // chunk groups per subband block; DM tiles
+    int cg0;                // first chunk group of this launch
     int chirp_ref;
     float sign;
     double f_centre, bw, delta, kk;   // MHz, MHz, bw/N MHz, 1e6 k_DM
@@ -184,7 +205,7 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
     const int ci = lw % a.inner;
     const int rest = lw / a.inner;
     const int dt = rest % a.ndt;
-    const int cg = (rest / a.ndt) * a.inner + ci;
+    const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
 
     const int t = threadIdx.x;
     const int f = t / T, tt = t % T;
@@ -203,8 +224,9 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
     for (int q = 0; q < 16; ++q)
         raw[q] = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
 
-    // DM-independent part of Eq. 1 per bin, in cycles per unit DM:
-    //   1e6 k_DM nu^2 / (nu0^2 (nu0 + nu)),  nu = offset from nu0 (MHz)
+    // DM-independent part of Eq. 1 per bin: g2 = 2 * sign * 1e6 k_DM nu^2 /
+    // (nu0^2 (nu0 + nu)), nu = offset from nu0 in MHz, so that for DM d the
+    // transfer function exp(sign 2 pi i DM g) = exp(i pi DM g2).
     const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
     double nu0, off;
     if (a.chirp_ref == 0) {
@@ -214,12 +236,12 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
         nu0 = fs;
         off = (double)c * M - 0.5 * a.n;
     }
-    const double scale = a.kk / (nu0 * nu0);
-    double g[16];
+    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
+    double g2[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
         const double nu = ((double)(tt + T * q) + off) * a.delta;
-        g[q] = scale * nu * nu / (nu0 + nu);
+        g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
     const cdmt::LdsPadded lds{sh + f * STRIDE};
@@ -233,14 +255,18 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
         cpair v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const double ph = dm * g[q];
-            const float u = (float)(ph - rint(ph));    // cycles in [-1/2, 1/2]
+            // phase in half-cycles, reduced in FP64 to n + r with |r| <= 1/2
+            const double t = dm * g2[q];
+            const double n = rint(t);
             float sn, cs;
-            sincospif(2.0f * u, &sn, &cs);
+            sincos_pi(static_cast<float>(t - n), sn, cs);
+            const int flip = static_cast<int>(n) << 31;      // (-1)^n
+            sn = __int_as_float(__float_as_int(sn) ^ flip);
+            cs = __int_as_float(__float_as_int(cs) ^ flip);
             // swap halves per channel: bin i -> transform input (i + M/2) mod M
-            v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, a.sign * sn));
+            v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, sn));
         }
-        cdmt::Stage<M, 1, +1>::run(v, tt, lds, twiddles(M));
+        cdmt::wg_fft<M, +1>(v, tt, lds);
 
         // detect; channel sample m = tt + T q
 #pragma unroll
@@ -290,6 +316,25 @@ int ensure_twiddles() {
     if (hipMemcpyToSymbol(HIP_SYMBOL(g_twiddle), h.data(), sizeof(float2) * h.size()) !=
         hipSuccess)
         return CDMT_E_DEVICE;
+    // row tables: family r, table for sub-transform length L at entry L,
+    // row k = exp(+2 pi i k q / L), q < r
+    std::vector<float2> st(4 * cdmt::kStageFamily, make_float2(0.f, 0.f));
+    for (int fam = 0; fam < 4; ++fam) {
+        const int r = 2 << fam;
+        for (int len = r; len < cdmt::kStageFamily; len <<= 1) {
+            for (int k = 0; k < len / r; ++k) {
+                for (int q = 0; q < r; ++q) {
+                    const long long e = ((long long)k * q) % len;
+                    const double a = 2.0 * M_PI * ((double)e / (double)len);
+                    st[fam * cdmt::kStageFamily + len + k * r + q] =
+                        make_float2((float)std::cos(a), (float)std::sin(a));
+                }
+            }
+        }
+    }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(cdmt::g_stage_tw), st.data(),
+                          sizeof(float2) * st.size()) != hipSuccess)
+        return CDMT_E_DEVICE;
     g_init_done[dev] = 1;
     return CDMT_OK;
 }
@@ -307,7 +352,7 @@ int ilog2(long long v) {
 struct cdmt_plan_s {
     int nsub, nfft, noverlap, nchan, ndec;
     double f_centre, bw;
-    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 4;
+    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 8;
     int m, nd, tblk, n1, n2;
 };
 
@@ -339,7 +384,8 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
     const long long bsn = (long long)nblock * p->nsub;
     const long long gcol = bsn * (p->n1 / (4096 / p->n2));
     const long long grow = bsn * (p->n2 / (4096 / p->n1));
-    if (gcol > 0x7fffffffLL || grow > 0x7fffffffLL)
+    // a dispatch covers at most 2^32 - 1 work-items
+    if (gcol * 256 > 0xffffffffLL || grow * 256 > 0xffffffffLL)
         return CDMT_E_SHAPE;
     switch (p->n2) {
     case 64: launch_col<64>(a, p->input_kind, (int)gcol, st); break;
@@ -357,10 +403,16 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
     return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
 }
 
+// A dispatch covers at most 2^32 - 1 work-items, so large jobs are split into
+// several launches: by DM (at most kMaxDmPerLaunch per launch, passed by
+// value) and, when the grid would still be too large, by chunk groups.
 template <int M>
 int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t st) {
     constexpr int WG = M >= 8192 ? 512 : 256;
     constexpr int C = WG / (M / 16);
+    constexpr long long kMaxGroups = 0xffffffffLL / WG;
+    const long long ncg = (a0.nchunks + C - 1) / C;
+    const int inner = a0.nchan >= C ? a0.nchan / C : 1;
     for (int first = 0; first < ndm; first += kMaxDmPerLaunch) {
         FusedArgs a = a0;
         const int cnt = ndm - first < kMaxDmPerLaunch ? ndm - first : kMaxDmPerLaunch;
@@ -370,15 +422,18 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
             dl.dm[i] = dms[first + i];
         a.ndm = cnt;
         a.out = a0.out + (long long)first * a0.ntime_out * a0.nch_out;
-        const long long ncg = (a.nchunks + C - 1) / C;
-        a.inner = a.nchan >= C ? a.nchan / C : 1;
+        a.inner = inner;
         a.ndt = (cnt + a.dm_tile - 1) / a.dm_tile;
-        const long long grid = ncg * a.ndt;
-        if (grid > 0x7fffffffLL)
+        long long per = kMaxGroups / a.ndt / inner * inner;   // chunk groups per launch
+        if (per < inner)
             return CDMT_E_SHAPE;
-        fused_dedisperse<M><<<(int)grid, WG, 0, st>>>(a, dl);
-        if (hipGetLastError() != hipSuccess)
-            return CDMT_E_DEVICE;
+        for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
+            const long long n = ncg - cg0 < per ? ncg - cg0 : per;
+            a.cg0 = (int)cg0;
+            fused_dedisperse<M><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
+            if (hipGetLastError() != hipSuccess)
+                return CDMT_E_DEVICE;
+        }
     }
     return CDMT_OK;
 }
@@ -419,6 +474,17 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
 }
 
 int check_plan(const cdmt_plan_s *p) { return p ? CDMT_OK : CDMT_E_ARG; }
+
+// Upper bound of |phase| in half-cycles per unit DM over every bin of the
+// plan (Eq. 1 at the largest offset from nu0 in the lowest subband).  The
+// kernel keeps the integer part of the phase in an int, so |DM| times this
+// must stay below 2^30.
+double max_half_cycles_per_dm(const cdmt_plan_s *p) {
+    const double f_lo = p->f_centre - p->nsub * p->bw / 2;
+    const double half = p->chirp_ref == 0 ? p->bw / (2.0 * p->nchan) : p->bw / 2;
+    const double nu0 = f_lo + half;
+    return 2.0 * 1e6 * kKdm * half * half / (nu0 * nu0 * f_lo);
+}
 
 int workspace_bytes(const cdmt_plan_s *p, int nblock, size_t *bytes) {
     if (nblock < 0)
@@ -599,8 +665,9 @@ int cdmt_dedisperse_spectra(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock
         return CDMT_OK;
     if (!dm_list || !out)
         return CDMT_E_ARG;
+    const double bound = max_half_cycles_per_dm(p);
     for (int i = 0; i < ndm; ++i)
-        if (!std::isfinite(dm_list[i]))
+        if (!std::isfinite(dm_list[i]) || std::fabs(dm_list[i]) * bound >= 1073741824.0)
             return CDMT_E_ARG;
     if ((st = ensure_twiddles()))
         return st;

@@ -13,9 +13,8 @@
 // order, read back in the next stage's input order); the first stage reads
 // registers and the last leaves its outputs in registers.
 //
-// Twiddles come from a table of exp(+2 pi i n / P), n in [0, P), held per
-// transform size in device memory and computed on the host in double
-// precision (the forward sign conjugates on the fly).
+// Twiddles come from per-stage row tables (below), computed on the host in
+// double precision; the forward sign conjugates them on the fly.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -194,8 +193,28 @@ struct LdsInterleaved {
 };
 
 // ---------------------------------------------------------------------------
+// Twiddle row tables.  For a stage of radix r that completes sub-transforms
+// of length L = NS * r, lane butterfly j needs exp(+2 pi i k q / L) for
+// k = j mod NS and q = 0..r-1.  Row k of the table for (L, r) holds exactly
+// these r values, so a lane fetches its twiddles with r/2 16-byte loads.
+// Family r (r = 2, 4, 8, 16) occupies 16384 entries; the table for L starts
+// at entry L of its family (L <= 8192).  Filled once per device from double
+// precision on the host.
+constexpr int kStageFamily = 16384;
+__device__ __align__(16) float2 g_stage_tw[4 * kStageFamily];
+
+template <int r>
+__device__ __forceinline__ const float2 *stage_table(int len) {
+    constexpr int fam = r == 2 ? 0 : r == 4 ? 1 : r == 8 ? 2 : 3;
+    return g_stage_tw + fam * kStageFamily + len;
+}
+
+// ---------------------------------------------------------------------------
 // One Stockham stage (and, recursively, the rest) of a P-point transform with
-// sign S.  NS = product of the radices already applied.
+// sign S.  NS = product of the radices already applied.  w holds this
+// stage's twiddles (w[u*r + q] for butterfly u, input q); the next stage's
+// rows are fetched before the LDS exchange so that their latency overlaps
+// the barrier.
 template <int P, int NS, int S>
 struct Stage {
     static constexpr int R = 16;
@@ -204,9 +223,26 @@ struct Stage {
     static constexpr int U = R / r;          // butterflies per lane
     static constexpr bool LAST = (NS * r == P);
 
+    __device__ __forceinline__ static void load_twiddles(float2 (&w)[16], int tt) {
+        if constexpr (NS > 1) {
+            const float2 *tab = stage_table<r>(NS * r);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = (tt + T * u) & (NS - 1);
+                const float4 *row = reinterpret_cast<const float4 *>(tab + k * r);
+#pragma unroll
+                for (int h = 0; h < r / 2; ++h) {
+                    const float4 x = row[h];
+                    w[u * r + 2 * h] = make_float2(x.x, x.y);
+                    w[u * r + 2 * h + 1] = make_float2(x.z, x.w);
+                }
+            }
+        }
+    }
+
     template <class Lds>
     __device__ __forceinline__ static void run(cpair (&v)[16], int tt, const Lds &lds,
-                                               const float2 *__restrict__ tw) {
+                                               const float2 (&w)[16]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = tt + T * u;
@@ -218,10 +254,10 @@ struct Stage {
             if constexpr (NS > 1) {
 #pragma unroll
                 for (int q = 1; q < r; ++q) {
-                    float2 w = tw[k * q * (P / (NS * r))];
+                    float2 tw = w[u * r + q];
                     if constexpr (S < 0)
-                        w.y = -w.y;
-                    a[q] = pmul(a[q], w);
+                        tw.y = -tw.y;
+                    a[q] = pmul(a[q], tw);
                 }
             }
             dft<r, S>(a);
@@ -237,14 +273,25 @@ struct Stage {
             }
         }
         if constexpr (!LAST) {
+            using Next = Stage<P, NS * r, S>;
+            float2 wn[16];
+            Next::load_twiddles(wn, tt);
             __syncthreads();
 #pragma unroll
             for (int s = 0; s < R; ++s)
                 v[s] = lds.load(tt + T * s);
             __syncthreads();
-            Stage<P, NS * r, S>::run(v, tt, lds, tw);
+            Next::run(v, tt, lds, wn);
         }
     }
 };
+
+// Whole P-point transform of the lane's registers (first stage has no
+// twiddles).
+template <int P, int S, class Lds>
+__device__ __forceinline__ void wg_fft(cpair (&v)[16], int tt, const Lds &lds) {
+    float2 w0[16];
+    Stage<P, 1, S>::run(v, tt, lds, w0);
+}
 
 }  // namespace cdmt
