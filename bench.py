@@ -31,6 +31,27 @@ HBM_PEAK_GBS = 8000.0
 VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 
 
+PROFILE = os.path.join(ROOT, "profiles", "fused_dedisperse_lofar_hba_288sub_128dm.md")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    import re
+    try:
+        text = open(PROFILE).read()
+        blob = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
+    except (OSError, AttributeError, ValueError):
+        return None
+    src = b"".join(open(os.path.join(ROOT, "paper_1607_00909_amd", "csrc", f), "rb").read()
+                   for f in ("cdmt.hip", "fft_core.hpp"))
+    if hashlib.sha256(src).hexdigest()[:16] != blob.get("source_sha256_16"):
+        return None
+    t = blob["traffic"].get(kernel)
+    return None if t is None else (t["fetch_GB"] + t["write_GB"]) * 1e9
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -191,7 +212,7 @@ def main():
         "roofline": {"kernel": "fused_dedisperse", "bound": "alu",
                      "achieved": round(achieved, 3), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4),
-                     "traffic": None,
+                     "traffic": measured_traffic("fused_dedisperse<%d>" % w.m),
                      "hbm_algorithmic_GBs": round(fused_bytes / fus_avg / 1e9, 1),
                      "hbm_frac": round(fused_bytes / fus_avg / 1e9 / HBM_PEAK_GBS, 4)},
         "kernels_ms": {"forward (fwd_col+fwd_row)": round(fwd_avg * 1e3, 3),
