@@ -173,6 +173,35 @@ __device__ __forceinline__ void sincos_pi(float r, float &s, float &c) {
     c = fmaf(pc, r2, 1.0f);
 }
 
+// exp(i pi t) for a phase t in half-cycles, in double precision: t is reduced
+// to n + r with |r| <= 1/2, sin(pi r) and cos(pi r) come from odd / even
+// polynomials fitted for this library (Lawson's method in float64; max error
+// 8e-14 and 5e-15), and (-1)^n is applied as a sign.  Rounded to float.
+__device__ __forceinline__ float2 cis_pi_f64(double t) {
+    const double n = rint(t);
+    const double r = t - n;
+    const double r2 = r * r;
+    double ps = 0.000447492634787997;
+    ps = fma(ps, r2, -0.007364005763000102);
+    ps = fma(ps, r2, 0.08214479472358047);
+    ps = fma(ps, r2, -0.5992644339392923);
+    ps = fma(ps, r2, 2.5501640359072306);
+    ps = fma(ps, r2, -5.167712779988032);
+    ps = fma(ps, r2, 3.1415926535896257);
+    double pc = -0.00010031723352996529;
+    pc = fma(pc, r2, 0.0019277873522597125);
+    pc = fma(pc, r2, -0.025806505139857543);
+    pc = fma(pc, r2, 0.23533058404112456);
+    pc = fma(pc, r2, -1.3352627658364828);
+    pc = fma(pc, r2, 4.058712126320176);
+    pc = fma(pc, r2, -4.934802200543524);
+    pc = fma(pc, r2, 0.9999999999999983);
+    const int flip = static_cast<int>(n) << 31;
+    const float sn = __int_as_float(__float_as_int(static_cast<float>(ps * r)) ^ flip);
+    const float cs = __int_as_float(__float_as_int(static_cast<float>(pc)) ^ flip);
+    return make_float2(cs, sn);
+}
+
 struct FusedArgs {
     const cpair *spec;      // [block][subband][N]
     float *out;             // first DM of this launch: [ndm][ntime_out][nsub*nchan]
@@ -181,6 +210,7 @@ struct FusedArgs {
     int nd_half, ndec, tblk, nch_out;
     int inner, ndt;         // chunk groups per subband block; DM tiles
     int cg0;                // first chunk group of this launch
+    double dm_step;         // DM spacing when the list is an arithmetic progression
     int chirp_ref;
     float sign;
     double f_centre, bw, delta, kk;   // MHz, MHz, bw/N MHz, 1e6 k_DM
@@ -192,7 +222,10 @@ struct DmList {
 
 // Transfer function, FFT, detection and downsampling for C = WG/T channel
 // chunks of M bins and a tile of DMs.
-template <int M>
+// RECUR: the launch's DM list is an arithmetic progression with step a.dm_step,
+// so within a tile the chirped spectrum advances by one factor per DM:
+// P(d+1) = P(d) exp(i pi dm_step g2), both factors from FP64 sincospi.
+template <int M, bool RECUR>
 __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedArgs a,
                                                                           DmList dl) {
     constexpr int WG = M >= 8192 ? 512 : 256;
@@ -250,21 +283,40 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
     const int d0 = dt * a.dm_tile;
     const int d1 = min(a.ndm, d0 + a.dm_tile);
 
-    for (int d = d0; d < d1; ++d) {
-        const double dm = dl.dm[d];
-        cpair v[16];
+    float2 step[16];
+    if constexpr (RECUR) {
+        // P(d0) = raw exp(i pi dm(d0) g2) and the per-DM step, in double
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            // phase in half-cycles, reduced in FP64 to n + r with |r| <= 1/2
-            const double t = dm * g2[q];
-            const double n = rint(t);
-            float sn, cs;
-            sincos_pi(static_cast<float>(t - n), sn, cs);
-            const int flip = static_cast<int>(n) << 31;      // (-1)^n
-            sn = __int_as_float(__float_as_int(sn) ^ flip);
-            cs = __int_as_float(__float_as_int(cs) ^ flip);
-            // swap halves per channel: bin i -> transform input (i + M/2) mod M
-            v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, sn));
+            raw[q] = cdmt::pmul(raw[q], cis_pi_f64(dl.dm[d0] * g2[q]));
+            step[q] = cis_pi_f64(a.dm_step * g2[q]);
+        }
+    }
+
+    for (int d = d0; d < d1; ++d) {
+        cpair v[16];
+        if constexpr (RECUR) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                // swap halves per channel: bin i -> transform input (i + M/2) mod M
+                v[q ^ 8] = raw[q];
+                raw[q] = cdmt::pmul(raw[q], step[q]);
+            }
+        } else {
+            const double dm = dl.dm[d];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                // phase in half-cycles, reduced in FP64 to n + r with |r| <= 1/2
+                const double t = dm * g2[q];
+                const double n = rint(t);
+                float sn, cs;
+                sincos_pi(static_cast<float>(t - n), sn, cs);
+                const int flip = static_cast<int>(n) << 31;      // (-1)^n
+                sn = __int_as_float(__float_as_int(sn) ^ flip);
+                cs = __int_as_float(__float_as_int(cs) ^ flip);
+                // swap halves per channel: bin i -> transform input (i + M/2) mod M
+                v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, sn));
+            }
         }
         cdmt::wg_fft<M, +1>(v, tt, lds);
 
@@ -277,12 +329,26 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
         __syncthreads();
         if (valid) {
             float *o = a.out + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + col;
-            for (int tq = tt; tq < a.tblk; tq += T) {
-                const float *p = inten + a.nd_half + tq * a.ndec;
-                float acc = 0.f;
-                for (int q = 0; q < a.ndec; ++q)
-                    acc += p[q];
-                o[(long long)tq * a.nch_out] = acc;
+            if (((a.ndec | a.nd_half) & 3) == 0) {
+                // 16-byte LDS reads when the summed runs are 4-float aligned
+                const int n4 = a.ndec >> 2;
+                for (int tq = tt; tq < a.tblk; tq += T) {
+                    const float4 *p = reinterpret_cast<const float4 *>(inten + a.nd_half) + tq * n4;
+                    float acc = 0.f;
+                    for (int q = 0; q < n4; ++q) {
+                        const float4 x = p[q];
+                        acc += (x.x + x.y) + (x.z + x.w);
+                    }
+                    o[(long long)tq * a.nch_out] = acc;
+                }
+            } else {
+                for (int tq = tt; tq < a.tblk; tq += T) {
+                    const float *p = inten + a.nd_half + tq * a.ndec;
+                    float acc = 0.f;
+                    for (int q = 0; q < a.ndec; ++q)
+                        acc += p[q];
+                    o[(long long)tq * a.nch_out] = acc;
+                }
             }
         }
         __syncthreads();
@@ -352,7 +418,7 @@ int ilog2(long long v) {
 struct cdmt_plan_s {
     int nsub, nfft, noverlap, nchan, ndec;
     double f_centre, bw;
-    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 8;
+    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 8, chirp_exact = 0;
     int m, nd, tblk, n1, n2;
 };
 
@@ -403,6 +469,30 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
     return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
 }
 
+// Upper bound of |phase| in half-cycles per unit DM over every bin of the
+// plan (Eq. 1 at the largest offset from nu0 in the lowest subband).  The
+// kernel keeps the integer part of the phase in an int, so |DM| times this
+// must stay below 2^30.
+double max_half_cycles_per_dm(const cdmt_plan_s *p) {
+    const double f_lo = p->f_centre - p->nsub * p->bw / 2;
+    const double half = p->chirp_ref == 0 ? p->bw / (2.0 * p->nchan) : p->bw / 2;
+    const double nu0 = f_lo + half;
+    return 2.0 * 1e6 * kKdm * half * half / (nu0 * nu0 * f_lo);
+}
+
+// True when dm[i] = dm[0] + i (dm[1] - dm[0]) for every i to within tol (the
+// transfer-function recurrence then reproduces each DM's phase to within
+// tol times the largest phase per unit DM).
+bool arithmetic(const double *dm, int n, double tol) {
+    const double step = dm[1] - dm[0];
+    if (step == 0.0)
+        return false;
+    for (int i = 2; i < n; ++i)
+        if (std::fabs(dm[i] - (dm[0] + i * step)) > tol)
+            return false;
+    return true;
+}
+
 // A dispatch covers at most 2^32 - 1 work-items, so large jobs are split into
 // several launches: by DM (at most kMaxDmPerLaunch per launch, passed by
 // value) and, when the grid would still be too large, by chunk groups.
@@ -424,13 +514,19 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
         a.out = a0.out + (long long)first * a0.ntime_out * a0.nch_out;
         a.inner = inner;
         a.ndt = (cnt + a.dm_tile - 1) / a.dm_tile;
+        const bool recur = a0.dm_step != 0.0 && a.dm_tile > 1 && cnt > 1 &&
+                           arithmetic(dl.dm, cnt, a0.dm_step);
+        a.dm_step = recur ? dl.dm[1] - dl.dm[0] : 0.0;
         long long per = kMaxGroups / a.ndt / inner * inner;   // chunk groups per launch
         if (per < inner)
             return CDMT_E_SHAPE;
         for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
             const long long n = ncg - cg0 < per ? ncg - cg0 : per;
             a.cg0 = (int)cg0;
-            fused_dedisperse<M><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
+            if (recur)
+                fused_dedisperse<M, true><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
+            else
+                fused_dedisperse<M, false><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
         }
@@ -460,6 +556,9 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
     a.bw = p->bw;
     a.delta = p->bw / p->nfft;
     a.kk = 1e6 * kKdm;
+    // recurrence allowed when every DM sits on the progression to within a
+    // phase error of 1e-7 half-cycles (dm_step carries the tolerance here)
+    a.dm_step = p->chirp_exact ? 0.0 : 1e-7 / max_half_cycles_per_dm(p);
     switch (p->m) {
     case 64: return launch_fused_m<64>(a, dms, ndm, st);
     case 128: return launch_fused_m<128>(a, dms, ndm, st);
@@ -475,16 +574,6 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
 
 int check_plan(const cdmt_plan_s *p) { return p ? CDMT_OK : CDMT_E_ARG; }
 
-// Upper bound of |phase| in half-cycles per unit DM over every bin of the
-// plan (Eq. 1 at the largest offset from nu0 in the lowest subband).  The
-// kernel keeps the integer part of the phase in an int, so |DM| times this
-// must stay below 2^30.
-double max_half_cycles_per_dm(const cdmt_plan_s *p) {
-    const double f_lo = p->f_centre - p->nsub * p->bw / 2;
-    const double half = p->chirp_ref == 0 ? p->bw / (2.0 * p->nchan) : p->bw / 2;
-    const double nu0 = f_lo + half;
-    return 2.0 * 1e6 * kKdm * half * half / (nu0 * nu0 * f_lo);
-}
 
 int workspace_bytes(const cdmt_plan_s *p, int nblock, size_t *bytes) {
     if (nblock < 0)
@@ -582,6 +671,11 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
             return CDMT_E_ARG;
         p->dm_tile = value;
         return CDMT_OK;
+    case CDMT_OPT_CHIRP_EXACT:
+        if (value != 0 && value != 1)
+            return CDMT_E_ARG;
+        p->chirp_exact = value;
+        return CDMT_OK;
     default:
         return CDMT_E_ARG;
     }
@@ -596,6 +690,7 @@ int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
     case CDMT_OPT_SIGN: *value = p->sign; return CDMT_OK;
     case CDMT_OPT_PRECISION: *value = p->precision; return CDMT_OK;
     case CDMT_OPT_DM_TILE: *value = p->dm_tile; return CDMT_OK;
+    case CDMT_OPT_CHIRP_EXACT: *value = p->chirp_exact; return CDMT_OK;
     default: return CDMT_E_ARG;
     }
 }

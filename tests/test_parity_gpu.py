@@ -69,22 +69,25 @@ def _tiny_cfg(chirp_ref):
                          chirp_ref=chirp_ref, sign=-1)
 
 
+@pytest.mark.parametrize("exact", [0, 1], ids=["recurrence", "exact"])
 @pytest.mark.parametrize("chirp_ref", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
-def test_tiny_workload_parity_and_recompression(hip_lib, chirp_ref):
+def test_tiny_workload_parity_and_recompression(hip_lib, chirp_ref, exact):
     """8 subbands (120.0-121.5625 MHz), cf32 noise sigma 1 plus a 20-sigma
     impulse dispersed at DM 10, nfft 16384 / noverlap 4096, 4 blocks, DMs
-    0..15, 8 channels, x4 downsampling."""
+    0..15, 8 channels, x4 downsampling; transfer function evaluated per DM
+    (exact) or advanced through each DM tile (recurrence)."""
     w = synth.TINY
     cfg = _tiny_cfg(chirp_ref)
-    _say(f"tiny workload chirp_ref={chirp_ref}")
+    _say(f"tiny workload chirp_ref={chirp_ref} exact={exact}")
     t0 = w.tblk + w.tblk // 2
     v = _voltages(cfg, w.nblock, w.sigma, w.seed, "cf32",
                   pulses=[(w.extra["pulse_dm"], t0, w.pulse_amp_sigma * w.sigma)])
     ref = oracle.dedisperse(cfg, v, w.nblock, w.dms)
-    gpu = _run_gpu(hip_lib, cfg, v, w.nblock, w.dms, "cf32")
+    gpu = _run_gpu(hip_lib, cfg, v, w.nblock, w.dms, "cf32", chirp_exact=exact, dm_tile=16)
     assert gpu.shape == ref.shape
     e_norm, e_max = _errors(gpu, ref)
-    print(f"tiny chirp_ref={chirp_ref}: max_d normwise {e_norm:.3e}, max-abs/max {e_max:.3e}")
+    print(f"tiny chirp_ref={chirp_ref} exact={exact}: max_d normwise {e_norm:.3e}, "
+          f"max-abs/max {e_max:.3e}")
     assert e_norm <= TOL and e_max <= TOL
     # the pulse recompresses at the same (DM, t) on both sides
     sg, sr = gpu.sum(axis=2), ref.sum(axis=2)
@@ -121,16 +124,37 @@ def test_shapes_parity(hip_lib, case):
 
 
 def test_dm_tile_and_repeat_bitwise_identical(hip_lib):
-    """The result of a DM does not depend on how DMs are tiled per workgroup,
-    and repeated runs are bitwise identical (no atomics, no races)."""
-    w = synth.TINY
+    """With the transfer function evaluated per DM, the result of a DM does
+    not depend on how DMs are tiled per workgroup, and repeated runs are
+    bitwise identical (no atomics, no races).  The recurrence mode is also
+    repeatable bitwise and agrees with the exact mode to the parity bar."""
     cfg = _tiny_cfg(oracle.CHANNEL)
     _say("dm tile invariance")
     v = _voltages(cfg, 2, 1.0, 3, "cf32")
     dms = list(np.arange(13) * 1.25)
-    outs = [_run_gpu(hip_lib, cfg, v, 2, dms, "cf32", dm_tile=t) for t in (1, 3, 4, 16, 4)]
+    outs = [_run_gpu(hip_lib, cfg, v, 2, dms, "cf32", dm_tile=t, chirp_exact=1)
+            for t in (1, 3, 4, 16, 4)]
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])
+    rec = [_run_gpu(hip_lib, cfg, v, 2, dms, "cf32", dm_tile=t) for t in (16, 16, 3)]
+    np.testing.assert_array_equal(rec[0], rec[1])
+    for r in (rec[0], rec[2]):
+        e_norm, e_max = _errors(r, outs[0])
+        assert e_norm <= TOL and e_max <= TOL
+
+
+def test_non_uniform_dm_list_uses_exact_path(hip_lib):
+    """A DM list that is not an arithmetic progression (random, unsorted,
+    negative values) is evaluated per DM and matches the oracle."""
+    cfg = _tiny_cfg(oracle.SUBBAND)
+    _say("random DM list")
+    v = _voltages(cfg, 2, 1.0, 21, "cf32")
+    dms = list(np.random.default_rng(5).uniform(-20.0, 80.0, 11))
+    ref = oracle.dedisperse(cfg, v, 2, dms)
+    gpu = _run_gpu(hip_lib, cfg, v, 2, dms, "cf32", dm_tile=4)
+    e_norm, e_max = _errors(gpu, ref)
+    print(f"random DMs: max_d normwise {e_norm:.3e}, max-abs/max {e_max:.3e}")
+    assert e_norm <= TOL and e_max <= TOL
 
 
 def test_more_dms_than_one_launch(hip_lib):
@@ -147,12 +171,12 @@ def test_more_dms_than_one_launch(hip_lib):
 
 def test_forward_then_spectra_matches_one_call(hip_lib):
     """cdmt_forward + cdmt_dedisperse_spectra (two DM lists on one set of
-    spectra) equals cdmt_dedisperse."""
+    spectra) equals cdmt_dedisperse bitwise (transfer function per DM)."""
     torch = _torch()
     cfg = _tiny_cfg(oracle.SUBBAND)
     _say("forward + spectra split")
     v = _voltages(cfg, 2, 1.0, 8, "cf32")
-    plan = _plan(hip_lib, cfg, "cf32")
+    plan = _plan(hip_lib, cfg, "cf32", chirp_exact=1)
     xd = torch.from_numpy(v).cuda()
     whole = plan.dedisperse(xd, 2, [1.0, 2.0, 3.0]).cpu().numpy()
     ws = plan.workspace(2)

@@ -19,6 +19,30 @@ pytestmark = pytest.mark.gpu
 PAIRS = [(0, 0), (1, 1), (143, 19), (287, 38), (200, 7), (77, 30)]
 
 
+def _check_pairs(out, w, label):
+    cols_of = lambda s: [(w.nsub - 1 - s) * w.nchan + (w.nchan - 1 - c) for c in range(w.nchan)]
+    worst = 0.0
+    for s, b in PAIRS:
+        xs = _HOST[s]
+        cfg = oracle.Config(1, w.f_centre + (s - (w.nsub - 1) / 2) * w.bw, w.bw, w.nfft,
+                            w.noverlap, w.nchan, w.ndec)
+        key = (s, b)
+        if key not in _REF:
+            _REF[key] = oracle.subband_block(cfg, xs, 0, b, list(w.dms))   # [dm][t][c]
+        ref = _REF[key]
+        gpu = out[:, b * w.tblk:(b + 1) * w.tblk, cols_of(s)].double().cpu().numpy()
+        d = gpu - ref
+        e = np.sqrt((d ** 2).sum((1, 2)) / (ref ** 2).sum((1, 2))).max()
+        emax = np.abs(d).max() / np.abs(ref).max()
+        print(f"{label} pair s={s} b={b}: max_d normwise {e:.3e}, max-abs/max {emax:.3e}",
+              flush=True)
+        worst = max(worst, e, emax)
+    assert worst <= 1e-5
+
+
+_HOST, _REF = {}, {}
+
+
 def test_lofar_full_size_sampled_parity(hip_lib):
     import torch
     if not torch.cuda.is_available():
@@ -27,35 +51,40 @@ def test_lofar_full_size_sampled_parity(hip_lib):
     print(f"[gpu-case] LOFAR full size {w.nsub}x{w.ntime_in}, {len(w.dms)} DMs", flush=True)
     dev = torch.device("cuda:0")
     x = synth.device_noise("ci8", w.nsub, w.ntime_in, w.sigma, w.seed, dev)
-    plan = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
-                        input_kind=hip_lib.INPUT_CI8)
-    _, ntout, nch = plan.shape(w.nblock)
-    ws = plan.workspace(w.nblock, dev)
-    out = torch.full((len(w.dms), ntout, nch), float("nan"), device=dev)
-    plan.dedisperse(x, w.nblock, list(w.dms), out=out, workspace=ws)
-    torch.cuda.synchronize()
-    assert bool(torch.isfinite(out).all()), "some output samples were never written"
-    assert float(out.min()) >= 0.0
+    for s, _ in PAIRS:
+        _HOST[s] = x[s].cpu().numpy()[None]
 
-    cols_of = lambda s: [(w.nsub - 1 - s) * w.nchan + (w.nchan - 1 - c) for c in range(w.nchan)]
-    worst = 0.0
-    for s, b in PAIRS:
-        xs = x[s].cpu().numpy()[None]
-        cfg = oracle.Config(1, w.f_centre + (s - (w.nsub - 1) / 2) * w.bw, w.bw, w.nfft,
-                            w.noverlap, w.nchan, w.ndec)
-        ref = oracle.subband_block(cfg, xs, 0, b, list(w.dms))          # [dm][t][c]
-        gpu = out[:, b * w.tblk:(b + 1) * w.tblk, cols_of(s)].double().cpu().numpy()
-        d = gpu - ref
-        e = np.sqrt((d ** 2).sum((1, 2)) / (ref ** 2).sum((1, 2))).max()
-        emax = np.abs(d).max() / np.abs(ref).max()
-        print(f"pair s={s} b={b}: max_d normwise {e:.3e}, max-abs/max {emax:.3e}", flush=True)
-        worst = max(worst, e, emax)
-    assert worst <= 1e-5
+    def run(**kw):
+        plan = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                            input_kind=hip_lib.INPUT_CI8, **kw)
+        _, ntout, nch = plan.shape(w.nblock)
+        out = torch.full((len(w.dms), ntout, nch), float("nan"), device=dev)
+        plan.dedisperse(x, w.nblock, list(w.dms), out=out, workspace=ws)
+        torch.cuda.synchronize()
+        return out
+
+    ws = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                      input_kind=hip_lib.INPUT_CI8).workspace(w.nblock, dev)
+    # the benchmark's configuration: default DM tile, recurrence over the tile
+    out_a = run()
+    assert bool(torch.isfinite(out_a).all()), "some output samples were never written"
+    assert float(out_a.min()) >= 0.0
+    _check_pairs(out_a, w, "default")
+
+    # transfer function evaluated per DM
+    out_b = run(chirp_exact=1)
+    assert bool(torch.isfinite(out_b).all())
+    _check_pairs(out_b, w, "exact")
+    # the two modes agree over the whole output, DM by DM
+    rel = 0.0
+    for d in range(out_a.shape[0]):
+        a, b = out_a[d].double(), out_b[d].double()
+        rel = max(rel, float(((a - b) ** 2).sum().sqrt() / (b ** 2).sum().sqrt()))
+        del a, b
+    print(f"recurrence vs exact, whole output: max_d normwise {rel:.3e}", flush=True)
+    assert rel <= 1e-5
+    del out_a
 
     # DM tile 1: 128 DM tiles x 179712 chunks needs two launches
-    plan1 = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
-                         input_kind=hip_lib.INPUT_CI8, dm_tile=1)
-    out1 = torch.full_like(out, float("nan"))
-    plan1.dedisperse(x, w.nblock, list(w.dms), out=out1, workspace=ws)
-    torch.cuda.synchronize()
-    assert bool(torch.equal(out1, out))
+    out_c = run(dm_tile=1, chirp_exact=1)
+    assert bool(torch.equal(out_c, out_b))
