@@ -45,11 +45,14 @@ enum cdmt_opt {
     CDMT_OPT_CHIRP_REF = 1,  /* 0: nu0 = channel centre (default), 1: subband centre    */
     CDMT_OPT_SIGN = 2,       /* -1: dedisperse (default), +1: multiply by Eq. 1 as is   */
     CDMT_OPT_PRECISION = 3,  /* 0: FP32 (default); others: CDMT_E_UNSUPPORTED for now    */
-    CDMT_OPT_DM_TILE = 4,    /* DM trials per workgroup pass, 1..16 (default 8)         */
-    CDMT_OPT_CHIRP_EXACT = 5 /* 1: evaluate the transfer function afresh for every DM;
+    CDMT_OPT_DM_TILE = 4,    /* DM trials per workgroup pass, 1..16 (default 16)        */
+    CDMT_OPT_CHIRP_EXACT = 5,/* 1: evaluate the transfer function afresh for every DM;
                                 0 (default): when the DM list is an arithmetic
                                 progression, advance it by one complex factor per DM
                                 inside a tile (both factors from FP64 sincospi)        */
+    CDMT_OPT_LANE_BINS = 6   /* performance knob of the DM stage: spectral bins held per
+                                GPU lane, 16 (default) or 8 (twice the lanes per channel,
+                                half the registers; used for M_bin = 2048 and 4096)      */
 };
 
 /*

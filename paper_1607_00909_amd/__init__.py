@@ -23,7 +23,7 @@ CDMT_OK, CDMT_E_ARG, CDMT_E_SHAPE, CDMT_E_WORKSPACE, CDMT_E_DEVICE, CDMT_E_UNSUP
     0, -1, -2, -3, -4, -5
 # enum cdmt_opt
 CDMT_OPT_INPUT, CDMT_OPT_CHIRP_REF, CDMT_OPT_SIGN, CDMT_OPT_PRECISION, CDMT_OPT_DM_TILE, \
-    CDMT_OPT_CHIRP_EXACT = 0, 1, 2, 3, 4, 5
+    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS = 0, 1, 2, 3, 4, 5, 6
 INPUT_CF32, INPUT_CI8 = 0, 1
 CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
 
@@ -161,7 +161,7 @@ class Plan:
 
     def __init__(self, nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec, *,
                  input_kind=INPUT_CF32, chirp_ref=CHIRP_CHANNEL, sign=-1, dm_tile=None,
-                 chirp_exact=None):
+                 chirp_exact=None, lane_bins=None):
         self.handle = cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec)
         self.nsub, self.nfft, self.noverlap, self.nchan, self.ndec = \
             nsub, nfft, noverlap, nchan, ndec
@@ -172,6 +172,8 @@ class Plan:
             cdmt_plan_set(self.handle, CDMT_OPT_DM_TILE, dm_tile)
         if chirp_exact is not None:
             cdmt_plan_set(self.handle, CDMT_OPT_CHIRP_EXACT, int(chirp_exact))
+        if lane_bins is not None:
+            cdmt_plan_set(self.handle, CDMT_OPT_LANE_BINS, int(lane_bins))
         self.input_kind = input_kind
 
     def __del__(self):

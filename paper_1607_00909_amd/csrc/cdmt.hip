@@ -75,8 +75,11 @@ __global__ __launch_bounds__(256) void fwd_col(FwdArgs a) {
     constexpr int T = P / 16, C = 4096 / P;
     __shared__ cpair sh[P * C];
     const int groups = a.n1 / C;
-    const int g = blockIdx.x % groups;
-    const int bs = blockIdx.x / groups;          // block * nsub + subband
+    // neighbouring column groups share 128-byte lines of int8 input: keep
+    // them on one XCD (one L2)
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = lw % groups;
+    const int bs = lw / groups;                  // block * nsub + subband
     const int s = bs % a.nsub, b = bs / a.nsub;
     const int t = threadIdx.x, f = t % C, tt = t / C;
     const int n1 = g * C + f;
@@ -99,7 +102,7 @@ __global__ __launch_bounds__(256) void fwd_col(FwdArgs a) {
             v[q] = x[(long long)a.n1 * (tt + T * q)];
     }
     cdmt::LdsInterleaved<C> lds{sh + f};
-    cdmt::wg_fft<P, -1>(v, tt, lds);
+    cdmt::wg_fft<P, -1, 16>(v, tt, lds);
 
     // four-step twiddle exp(-2 pi i n1 k2 / N), then store row k2
     const float2 *twn = twiddles(a.n);
@@ -120,8 +123,9 @@ __global__ __launch_bounds__(256) void fwd_row(FwdArgs a) {
     constexpr int STRIDE = P + P / 16 + 1;    // odd: conflict-free transposed reads
     __shared__ cpair sh[C * STRIDE];
     const int groups = a.n2 / C;
-    const int g = blockIdx.x % groups;
-    const int bs = blockIdx.x / groups;
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int g = lw % groups;
+    const int bs = lw / groups;
     const int t = threadIdx.x;
     const int f = t / T, tt = t % T;          // lanes along the row: contiguous loads
     const int k2 = g * C + f;
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(256) void fwd_row(FwdArgs a) {
     for (int q = 0; q < 16; ++q)
         v[q] = y[tt + T * q];
     cdmt::LdsPadded lds{sh + f * STRIDE};
-    cdmt::wg_fft<P, -1>(v, tt, lds);
+    cdmt::wg_fft<P, -1, 16>(v, tt, lds);
 
     // X[k2 + N2 k1] with k1 = tt + T q.  Transpose through LDS so that
     // consecutive lanes store consecutive k2, i.e. consecutive bins.
@@ -225,13 +229,27 @@ struct DmList {
 // RECUR: the launch's DM list is an arithmetic progression with step a.dm_step,
 // so within a tile the chirped spectrum advances by one factor per DM:
 // P(d+1) = P(d) exp(i pi dm_step g2), both factors from FP64 sincospi.
-template <int M, bool RECUR>
-__global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedArgs a,
-                                                                          DmList dl) {
-    constexpr int WG = M >= 8192 ? 512 : 256;
-    constexpr int T = M / 16;
-    constexpr int C = WG / T;
-    constexpr int STRIDE = M + M / 16 + 1;
+//
+// R = bins per lane (16: 256-lane workgroups, radix-16 stages; 8: 512-lane
+// workgroups at M = 4096, radix-8 stages, half the registers per lane).
+template <int M, int R>
+struct FusedShape {
+    static constexpr int T = M / R;                       // lanes per chunk
+    static constexpr int WG = T > 256 ? T : 256;
+    static constexpr int C = WG / T;                      // chunks per workgroup
+    static constexpr int STRIDE = M + M / R + 1;          // LDS per chunk (pairs)
+    // minimum waves per SIMD requested from the compiler: R = 8 asks for 4
+    // (two 512-lane workgroups per CU, at most 128 VGPRs per lane)
+    static constexpr int MIN_WAVES = R == 8 ? 4 : 1;
+};
+
+template <int M, int R, bool RECUR>
+__global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVES)) void fused_dedisperse(FusedArgs a,
+                                                                         DmList dl) {
+    using Sh = FusedShape<M, R>;
+    constexpr int T = Sh::T;
+    constexpr int C = Sh::C;
+    constexpr int STRIDE = Sh::STRIDE;
     __shared__ cpair sh[C * STRIDE];
 
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
@@ -251,10 +269,10 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
     const int b = bs / a.nsub;
 
     // this channel's M bins, both pols, increasing frequency
-    cpair raw[16];
+    cpair raw[R];
     const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
+    for (int q = 0; q < R; ++q)
         raw[q] = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
 
     // DM-independent part of Eq. 1 per bin: g2 = 2 * sign * 1e6 k_DM nu^2 /
@@ -270,42 +288,42 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
         off = (double)c * M - 0.5 * a.n;
     }
     const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
-    double g2[16];
+    double g2[R];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < R; ++q) {
         const double nu = ((double)(tt + T * q) + off) * a.delta;
         g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
-    const cdmt::LdsPadded lds{sh + f * STRIDE};
+    const cdmt::LdsPad<R> lds{sh + f * STRIDE};
     float *inten = reinterpret_cast<float *>(sh + f * STRIDE);
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
     const int d0 = dt * a.dm_tile;
     const int d1 = min(a.ndm, d0 + a.dm_tile);
 
-    float2 step[16];
+    float2 step[R];
     if constexpr (RECUR) {
         // P(d0) = raw exp(i pi dm(d0) g2) and the per-DM step, in double
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < R; ++q) {
             raw[q] = cdmt::pmul(raw[q], cis_pi_f64(dl.dm[d0] * g2[q]));
             step[q] = cis_pi_f64(a.dm_step * g2[q]);
         }
     }
 
     for (int d = d0; d < d1; ++d) {
-        cpair v[16];
+        cpair v[R];
         if constexpr (RECUR) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < R; ++q) {
                 // swap halves per channel: bin i -> transform input (i + M/2) mod M
-                v[q ^ 8] = raw[q];
+                v[q ^ (R / 2)] = raw[q];
                 raw[q] = cdmt::pmul(raw[q], step[q]);
             }
         } else {
             const double dm = dl.dm[d];
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
+            for (int q = 0; q < R; ++q) {
                 // phase in half-cycles, reduced in FP64 to n + r with |r| <= 1/2
                 const double t = dm * g2[q];
                 const double n = rint(t);
@@ -315,14 +333,14 @@ __global__ __launch_bounds__(M >= 8192 ? 512 : 256) void fused_dedisperse(FusedA
                 sn = __int_as_float(__float_as_int(sn) ^ flip);
                 cs = __int_as_float(__float_as_int(cs) ^ flip);
                 // swap halves per channel: bin i -> transform input (i + M/2) mod M
-                v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, sn));
+                v[q ^ (R / 2)] = cdmt::pmul(raw[q], make_float2(cs, sn));
             }
         }
         cdmt::wg_fft<M, +1>(v, tt, lds);
 
         // detect; channel sample m = tt + T q
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
+        for (int q = 0; q < R; ++q) {
             const cpair y = v[q];
             inten[tt + T * q] = y.x * y.x + y.y * y.y + y.z * y.z + y.w * y.w;
         }
@@ -418,7 +436,7 @@ int ilog2(long long v) {
 struct cdmt_plan_s {
     int nsub, nfft, noverlap, nchan, ndec;
     double f_centre, bw;
-    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 8, chirp_exact = 0;
+    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 16, chirp_exact = 0, lane_bins = 16;
     int m, nd, tblk, n1, n2;
 };
 
@@ -496,10 +514,10 @@ bool arithmetic(const double *dm, int n, double tol) {
 // A dispatch covers at most 2^32 - 1 work-items, so large jobs are split into
 // several launches: by DM (at most kMaxDmPerLaunch per launch, passed by
 // value) and, when the grid would still be too large, by chunk groups.
-template <int M>
+template <int M, int R>
 int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t st) {
-    constexpr int WG = M >= 8192 ? 512 : 256;
-    constexpr int C = WG / (M / 16);
+    constexpr int WG = FusedShape<M, R>::WG;
+    constexpr int C = FusedShape<M, R>::C;
     constexpr long long kMaxGroups = 0xffffffffLL / WG;
     const long long ncg = (a0.nchunks + C - 1) / C;
     const int inner = a0.nchan >= C ? a0.nchan / C : 1;
@@ -524,9 +542,9 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
             const long long n = ncg - cg0 < per ? ncg - cg0 : per;
             a.cg0 = (int)cg0;
             if (recur)
-                fused_dedisperse<M, true><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
+                fused_dedisperse<M, R, true><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
             else
-                fused_dedisperse<M, false><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
+                fused_dedisperse<M, R, false><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
         }
@@ -559,15 +577,18 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
     // recurrence allowed when every DM sits on the progression to within a
     // phase error of 1e-7 half-cycles (dm_step carries the tolerance here)
     a.dm_step = p->chirp_exact ? 0.0 : 1e-7 / max_half_cycles_per_dm(p);
+    const bool r8 = p->lane_bins == 8;
     switch (p->m) {
-    case 64: return launch_fused_m<64>(a, dms, ndm, st);
-    case 128: return launch_fused_m<128>(a, dms, ndm, st);
-    case 256: return launch_fused_m<256>(a, dms, ndm, st);
-    case 512: return launch_fused_m<512>(a, dms, ndm, st);
-    case 1024: return launch_fused_m<1024>(a, dms, ndm, st);
-    case 2048: return launch_fused_m<2048>(a, dms, ndm, st);
-    case 4096: return launch_fused_m<4096>(a, dms, ndm, st);
-    case 8192: return launch_fused_m<8192>(a, dms, ndm, st);
+    case 64: return launch_fused_m<64, 16>(a, dms, ndm, st);
+    case 128: return launch_fused_m<128, 16>(a, dms, ndm, st);
+    case 256: return launch_fused_m<256, 16>(a, dms, ndm, st);
+    case 512: return launch_fused_m<512, 16>(a, dms, ndm, st);
+    case 1024: return launch_fused_m<1024, 16>(a, dms, ndm, st);
+    case 2048: return r8 ? launch_fused_m<2048, 8>(a, dms, ndm, st)
+                         : launch_fused_m<2048, 16>(a, dms, ndm, st);
+    case 4096: return r8 ? launch_fused_m<4096, 8>(a, dms, ndm, st)
+                         : launch_fused_m<4096, 16>(a, dms, ndm, st);
+    case 8192: return launch_fused_m<8192, 16>(a, dms, ndm, st);
     default: return CDMT_E_UNSUPPORTED;
     }
 }
@@ -676,6 +697,11 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
             return CDMT_E_ARG;
         p->chirp_exact = value;
         return CDMT_OK;
+    case CDMT_OPT_LANE_BINS:
+        if (value != 8 && value != 16)
+            return CDMT_E_ARG;
+        p->lane_bins = value;
+        return CDMT_OK;
     default:
         return CDMT_E_ARG;
     }
@@ -691,6 +717,7 @@ int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
     case CDMT_OPT_PRECISION: *value = p->precision; return CDMT_OK;
     case CDMT_OPT_DM_TILE: *value = p->dm_tile; return CDMT_OK;
     case CDMT_OPT_CHIRP_EXACT: *value = p->chirp_exact; return CDMT_OK;
+    case CDMT_OPT_LANE_BINS: *value = p->lane_bins; return CDMT_OK;
     default: return CDMT_E_ARG;
     }
 }

@@ -5,10 +5,11 @@
 // once, so one twiddle or transfer-function factor serves two complex values.
 //
 // Transform layout: a P-point transform (P a power of two, 32 <= P <= 8192)
-// is spread over T = P/16 lanes; lane tt holds elements tt + T*slot in
-// registers v[slot], slot = 0..15, at the input and at the output (natural
-// order both ways).  Stages are Stockham autosort, decimation in time:
-// radix 16 while at least 16 elements remain, then one radix 2/4/8 stage.
+// is spread over T = P/R lanes (R = 8 or 16 elements per lane); lane tt holds
+// elements tt + T*slot in registers v[slot], slot = 0..R-1, at the input and
+// at the output (natural order both ways).  Stages are Stockham autosort,
+// decimation in time: radix R while at least R elements remain, then one
+// smaller radix.
 // Between stages the values go through LDS once (write in the stage's output
 // order, read back in the next stage's input order); the first stage reads
 // registers and the last leaves its outputs in registers.
@@ -175,13 +176,15 @@ __device__ __forceinline__ void dft(cpair *a) {
 // ---------------------------------------------------------------------------
 // LDS views of one transform's elements.
 
-// element e at base[e + e/16]: one padding slot per 16 elements keeps the
-// stride-16 writes of the first stage off a single bank group
-struct LdsPadded {
+// element e at base[e + e/PAD]: one padding slot per PAD elements keeps the
+// stride-R writes of the first stage spread over the banks (PAD = R)
+template <int PAD>
+struct LdsPad {
     cpair *base;
-    __device__ __forceinline__ void store(int e, cpair v) const { base[e + (e >> 4)] = v; }
-    __device__ __forceinline__ cpair load(int e) const { return base[e + (e >> 4)]; }
+    __device__ __forceinline__ void store(int e, cpair v) const { base[e + e / PAD] = v; }
+    __device__ __forceinline__ cpair load(int e) const { return base[e + e / PAD]; }
 };
+typedef LdsPad<16> LdsPadded;
 
 // element e of transform f at base[e*C + f]: several transforms interleaved,
 // consecutive lanes (consecutive f) touch consecutive addresses
@@ -211,19 +214,18 @@ __device__ __forceinline__ const float2 *stage_table(int len) {
 
 // ---------------------------------------------------------------------------
 // One Stockham stage (and, recursively, the rest) of a P-point transform with
-// sign S.  NS = product of the radices already applied.  w holds this
-// stage's twiddles (w[u*r + q] for butterfly u, input q); the next stage's
-// rows are fetched before the LDS exchange so that their latency overlaps
-// the barrier.
-template <int P, int NS, int S>
+// sign S, R elements per lane (R = 8 or 16).  NS = product of the radices
+// already applied.  w holds this stage's twiddles (w[u*r + q] for butterfly
+// u, input q); the next stage's rows are fetched before the LDS exchange so
+// that their latency overlaps the barrier.
+template <int P, int R, int NS, int S>
 struct Stage {
-    static constexpr int R = 16;
     static constexpr int T = P / R;
     static constexpr int r = (P / NS >= R) ? R : P / NS;
     static constexpr int U = R / r;          // butterflies per lane
     static constexpr bool LAST = (NS * r == P);
 
-    __device__ __forceinline__ static void load_twiddles(float2 (&w)[16], int tt) {
+    __device__ __forceinline__ static void load_twiddles(float2 (&w)[R], int tt) {
         if constexpr (NS > 1) {
             const float2 *tab = stage_table<r>(NS * r);
 #pragma unroll
@@ -241,8 +243,8 @@ struct Stage {
     }
 
     template <class Lds>
-    __device__ __forceinline__ static void run(cpair (&v)[16], int tt, const Lds &lds,
-                                               const float2 (&w)[16]) {
+    __device__ __forceinline__ static void run(cpair (&v)[R], int tt, const Lds &lds,
+                                               const float2 (&w)[R]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int j = tt + T * u;
@@ -273,8 +275,8 @@ struct Stage {
             }
         }
         if constexpr (!LAST) {
-            using Next = Stage<P, NS * r, S>;
-            float2 wn[16];
+            using Next = Stage<P, R, NS * r, S>;
+            float2 wn[R];
             Next::load_twiddles(wn, tt);
             __syncthreads();
 #pragma unroll
@@ -288,10 +290,10 @@ struct Stage {
 
 // Whole P-point transform of the lane's registers (first stage has no
 // twiddles).
-template <int P, int S, class Lds>
-__device__ __forceinline__ void wg_fft(cpair (&v)[16], int tt, const Lds &lds) {
-    float2 w0[16];
-    Stage<P, 1, S>::run(v, tt, lds, w0);
+template <int P, int S, int R, class Lds>
+__device__ __forceinline__ void wg_fft(cpair (&v)[R], int tt, const Lds &lds) {
+    float2 w0[R];
+    Stage<P, R, 1, S>::run(v, tt, lds, w0);
 }
 
 }  // namespace cdmt

@@ -90,6 +90,10 @@ def test_options(lib):
         cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_CHIRP_EXACT, 1)
         assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_CHIRP_EXACT) == 1
         assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_CHIRP_EXACT, 2) == cdmt.CDMT_E_ARG
+        assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_LANE_BINS) == 16
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_LANE_BINS, 8)
+        assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_LANE_BINS) == 8
+        assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_LANE_BINS, 4) == cdmt.CDMT_E_ARG
         for opt, val, want in ((cdmt.CDMT_OPT_SIGN, 0, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_INPUT, 2, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_DM_TILE, 0, cdmt.CDMT_E_ARG),

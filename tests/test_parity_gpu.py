@@ -69,24 +69,26 @@ def _tiny_cfg(chirp_ref):
                          chirp_ref=chirp_ref, sign=-1)
 
 
+@pytest.mark.parametrize("lane_bins", [16, 8])
 @pytest.mark.parametrize("exact", [0, 1], ids=["recurrence", "exact"])
 @pytest.mark.parametrize("chirp_ref", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
-def test_tiny_workload_parity_and_recompression(hip_lib, chirp_ref, exact):
+def test_tiny_workload_parity_and_recompression(hip_lib, chirp_ref, exact, lane_bins):
     """8 subbands (120.0-121.5625 MHz), cf32 noise sigma 1 plus a 20-sigma
     impulse dispersed at DM 10, nfft 16384 / noverlap 4096, 4 blocks, DMs
     0..15, 8 channels, x4 downsampling; transfer function evaluated per DM
     (exact) or advanced through each DM tile (recurrence)."""
     w = synth.TINY
     cfg = _tiny_cfg(chirp_ref)
-    _say(f"tiny workload chirp_ref={chirp_ref} exact={exact}")
+    _say(f"tiny workload chirp_ref={chirp_ref} exact={exact} lane_bins={lane_bins}")
     t0 = w.tblk + w.tblk // 2
     v = _voltages(cfg, w.nblock, w.sigma, w.seed, "cf32",
                   pulses=[(w.extra["pulse_dm"], t0, w.pulse_amp_sigma * w.sigma)])
     ref = oracle.dedisperse(cfg, v, w.nblock, w.dms)
-    gpu = _run_gpu(hip_lib, cfg, v, w.nblock, w.dms, "cf32", chirp_exact=exact, dm_tile=16)
+    gpu = _run_gpu(hip_lib, cfg, v, w.nblock, w.dms, "cf32", chirp_exact=exact, dm_tile=16,
+                   lane_bins=lane_bins)
     assert gpu.shape == ref.shape
     e_norm, e_max = _errors(gpu, ref)
-    print(f"tiny chirp_ref={chirp_ref} exact={exact}: max_d normwise {e_norm:.3e}, "
+    print(f"tiny chirp_ref={chirp_ref} exact={exact} bins={lane_bins}: max_d normwise {e_norm:.3e}, "
           f"max-abs/max {e_max:.3e}")
     assert e_norm <= TOL and e_max <= TOL
     # the pulse recompresses at the same (DM, t) on both sides
@@ -103,13 +105,17 @@ CASES = [
     (3, 16384, 1024, 16, 3, 2, "cf32", oracle.CHANNEL, -1, 6, 2),    # M = 1024, ndec 3
     (1, 32768, 8192, 8, 8, 2, "ci8", oracle.SUBBAND, -1, 9, 4),      # M = 4096, nfft 2^15
     (2, 65536, 15360, 16, 8, 2, "ci8", oracle.CHANNEL, -1, 9, 4),    # LOFAR chunk shape
+    (2, 65536, 15360, 16, 8, 2, "ci8", oracle.SUBBAND, -1, 9, 8, 8), # same, 8 bins per lane
+    (1, 32768, 4096, 16, 2, 2, "cf32", oracle.CHANNEL, 1, 5, 2, 8),  # M = 2048, 8 bins per lane
     (1, 131072, 16384, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 3, 1),  # M = 8192, nfft 2^17
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"M{c[1] // c[3]}-nfft{c[1]}-{c[6]}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"M{c[1] // c[3]}-nfft{c[1]}-{c[6]}-b{(c + (16,))[11]}"
+                                             for c in CASES])
 def test_shapes_parity(hip_lib, case):
-    nsub, nfft, nov, nchan, ndec, nblock, kind, ref_mode, sign, ndm, tile = case
+    nsub, nfft, nov, nchan, ndec, nblock, kind, ref_mode, sign, ndm, tile = case[:11]
+    bins = case[11] if len(case) > 11 else 16
     cfg = oracle.Config(nsub, 138.0, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec,
                         chirp_ref=ref_mode, sign=sign)
     _say(f"shapes case {case}")
@@ -117,7 +123,7 @@ def test_shapes_parity(hip_lib, case):
     v = _voltages(cfg, nblock, sigma, 11 + nfft, kind)
     dms = list(np.linspace(-3.0, 60.0, ndm))
     ref = oracle.dedisperse(cfg, v, nblock, dms)
-    gpu = _run_gpu(hip_lib, cfg, v, nblock, dms, kind, dm_tile=tile)
+    gpu = _run_gpu(hip_lib, cfg, v, nblock, dms, kind, dm_tile=tile, lane_bins=bins)
     e_norm, e_max = _errors(gpu, ref)
     print(f"case {case}: max_d normwise {e_norm:.3e}, max-abs/max {e_max:.3e}")
     assert e_norm <= TOL and e_max <= TOL
