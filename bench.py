@@ -67,7 +67,7 @@ def fused_flops_per_bin(m: int) -> float:
     return 2 * (6 + 5 * math.log2(m) + 3)
 
 
-def cpu_baseline(w, x_dev, npairs: int, threads: int):
+def cpu_baseline(w, x_dev, npairs: int, threads: int, outputs=None):
     """Oracle (FP64, C) on a bounded sample of (subband, block) pairs with all
     DMs, extrapolated linearly to the whole job."""
     import numpy as np
@@ -93,15 +93,25 @@ def cpu_baseline(w, x_dev, npairs: int, threads: int):
     oracle._load()
     t0 = time.perf_counter()
     with ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, pairs))
+        refs = list(ex.map(one, pairs))
     dt = time.perf_counter() - t0
+    errors = {}
+    for name, out in (outputs or {}).items():
+        worst_n = worst_m = 0.0
+        for (s, b), ref in zip(pairs, refs):
+            cols = [(w.nsub - 1 - s) * w.nchan + (w.nchan - 1 - c) for c in range(w.nchan)]
+            gpu = out[:, b * w.tblk:(b + 1) * w.tblk, cols].double().cpu().numpy()
+            d = gpu - ref
+            worst_n = max(worst_n, float(np.sqrt((d ** 2).sum((1, 2)) / (ref ** 2).sum((1, 2))).max()))
+            worst_m = max(worst_m, float(np.abs(d).max() / np.abs(ref).max()))
+        errors[name] = {"normwise_max_over_dm": worst_n, "maxabs_over_max": worst_m}
     total_pairs = w.nsub * w.nblock
     full_seconds = dt * total_pairs / len(pairs)
     value = len(w.dms) * w.data_seconds / full_seconds
     return {"value": value, "unit": "DM-s/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(pairs)} (subband, block) pairs x {len(w.dms)} DMs of the "
                       f"{total_pairs}-pair job, {dt:.1f} s wall on {threads} threads, "
-                      f"extrapolated linearly"}
+                      f"extrapolated linearly"}, errors
 
 
 def main():
@@ -112,9 +122,13 @@ def main():
     ap.add_argument("--workload", default="lofar-hba-288sub-128dm")
     ap.add_argument("--dm-tile", type=int, default=None)
     ap.add_argument("--lane-bins", type=int, default=None, choices=[8, 16])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"],
+                    help="backward-FFT arithmetic of the DM stage")
     ap.add_argument("--chirp-ref", choices=["channel", "subband"], default="channel")
-    ap.add_argument("--cpu-pairs", type=int, default=16)
+    ap.add_argument("--cpu-pairs", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the other DM-stage arithmetics (mixed vs FP32 plain)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration for profiles)")
     args = ap.parse_args()
@@ -141,6 +155,8 @@ def main():
     plan = cdmt.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
                      input_kind=kind, chirp_ref=chirp_ref, dm_tile=args.dm_tile,
                      lane_bins=args.lane_bins)
+    prec_code = {"fp32": 0, "bf16x3": 1, "fp16x3": 2}[args.precision]
+    cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, prec_code)
     dm_tile = cdmt.cdmt_plan_get(plan.handle, cdmt.CDMT_OPT_DM_TILE)
     lane_bins = cdmt.cdmt_plan_get(plan.handle, cdmt.CDMT_OPT_LANE_BINS)
     ws = plan.workspace(w.nblock, dev)
@@ -214,7 +230,7 @@ def main():
                    "nchan": w.nchan, "ndec": w.ndec, "nblock": w.nblock, "ndm": ndm,
                    "data_seconds": round(w.data_seconds, 6), "input": w.input_kind,
                    "chirp_ref": args.chirp_ref, "dm_tile": dm_tile, "lane_bins": lane_bins,
-                   "precision": "fp32",
+                   "precision": args.precision,
                    "parallelism": "none"},
         "roofline": {"kernel": "fused_dedisperse", "bound": "alu",
                      "achieved": round(achieved, 3), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
@@ -228,10 +244,43 @@ def main():
                        "forward_algorithmic_GBs": round(fwd_bytes / fwd_avg / 1e9, 1)},
         "realtime_factor": round(w.data_seconds / (elapsed / args.steps), 2),
     }
+    outputs = {args.precision: out}
+    if args.variants and w.m == 4096:
+        # the same job with the other backward-FFT arithmetics, same input
+        variants = {}
+        for name, code in (("fp32", 0), ("bf16x3", 1), ("fp16x3", 2)):
+            if name == args.precision:
+                continue
+            cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, code)
+            o2 = torch.empty_like(out)
+            plan.dedisperse_spectra(w.nblock, dms, o2, ws)
+            torch.cuda.synchronize()
+            ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+            t1 = time.perf_counter()
+            for i in range(args.steps):
+                ev[i][0].record(stream)
+                plan.dedisperse_spectra(w.nblock, dms, o2, ws)
+                ev[i][1].record(stream)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t1
+            ms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+            # normwise difference from the main run, DM by DM
+            rel = 0.0
+            for d in range(out.shape[0]):
+                a_, b_ = o2[d].double(), out[d].double()
+                rel = max(rel, float(((a_ - b_) ** 2).sum().sqrt() / (b_ ** 2).sum().sqrt()))
+            variants[name] = {"value": round(ndm * w.data_seconds * args.steps / (el + fwd_avg * args.steps), 2),
+                              "fused_ms": round(ms, 3),
+                              "normwise_vs_" + args.precision: rel}
+            outputs[name] = o2
+            log(f"variant {name}: fused {ms:.3f} ms, normwise vs {args.precision} {rel:.2e}")
+        cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, prec_code)
+        line["variants"] = variants
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads")
-        line["cpu_baseline"] = cpu_baseline(w, x, args.cpu_pairs, threads)
+        line["cpu_baseline"], errs = cpu_baseline(w, x, args.cpu_pairs, threads, outputs)
+        line["errors_vs_oracle"] = errs
     print(json.dumps(line), flush=True)
 
 

@@ -44,7 +44,11 @@ enum cdmt_opt {
     CDMT_OPT_INPUT = 0,      /* 0: complex float32 (default), 1: complex int8           */
     CDMT_OPT_CHIRP_REF = 1,  /* 0: nu0 = channel centre (default), 1: subband centre    */
     CDMT_OPT_SIGN = 2,       /* -1: dedisperse (default), +1: multiply by Eq. 1 as is   */
-    CDMT_OPT_PRECISION = 3,  /* 0: FP32 (default); others: CDMT_E_UNSUPPORTED for now    */
+    CDMT_OPT_PRECISION = 3,  /* backward-FFT arithmetic of the DM stage: 0 FP32 vector
+                                (default); 1 BF16x3, 2 FP16x3: radix-16 stages on the
+                                matrix cores with hi/lo split operands and FP32
+                                accumulation (M_bin = 4096 only, else
+                                CDMT_E_UNSUPPORTED)                                     */
     CDMT_OPT_DM_TILE = 4,    /* DM trials per workgroup pass, 1..16 (default 16)        */
     CDMT_OPT_CHIRP_EXACT = 5,/* 1: evaluate the transfer function afresh for every DM;
                                 0 (default): when the DM list is an arithmetic

@@ -374,6 +374,351 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
 }
 
 // ---------------------------------------------------------------------------
+// Split-precision matrix-core variant of the DM stage, M = 4096.
+//
+// Each radix-16 Stockham stage is the real 32x32 matrix
+//   A = [[Fr, -Fi], [Fi, Fr]] / 16,   F[r][q] = exp(+2 pi i r q / 16),
+// applied to 32 butterfly columns [Re x_0..15; Im x_0..15] with
+// v_mfma_f32_32x32x16_{f16,bf16} (K = 16: one instruction for the real-input
+// half of A, one for the imaginary-input half).  Both operands are split
+// into hi + lo parts in the 16-bit type and A_hi B_hi + A_hi B_lo + A_lo B_hi
+// accumulate in FP32.  Operand layouts (one wave, lane l, t = 0..7):
+//   A: lane l holds A[l % 32][8 (l / 32) + t]
+//   B: lane l holds B[8 (l / 32) + t][l % 32]
+//   D: lane l, element v holds D[8 (v / 4) + 4 (l / 32) + v % 4][l % 32]
+// so a lane owns inputs q = 8h + t (h = l / 32) of its column; the rows of A
+// are permuted so that it owns outputs r = 8h + u (u = 0..7), real and
+// imaginary parts in adjacent accumulator elements 2u, 2u + 1.  The 1/16 in A keeps every stage's
+// operands within the first stage's range; a per-chunk power-of-two scale
+// puts that range near 2^14 (exact, removed after detection), which keeps
+// FP16 operands finite and their lo parts mostly normal.
+//
+// Work per workgroup (256 lanes, 4 waves): one channel chunk of 4096 bins and
+// a tile of DMs.  Wave w, column c = l % 32 owns butterflies j_b = 64 w +
+// 32 b + c (b = 0, 1) in both polarisations: four 32-column tiles per stage.
+
+typedef _Float16 mx_h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 mx_b8 __attribute__((ext_vector_type(8)));
+typedef _Float16 mx_h2 __attribute__((ext_vector_type(2)));
+typedef __bf16 mx_b2 __attribute__((ext_vector_type(2)));
+typedef float mx_f2 __attribute__((ext_vector_type(2)));
+typedef float mx_f16 __attribute__((ext_vector_type(16)));
+
+template <bool BF>
+struct MxType;
+template <>
+struct MxType<false> {
+    typedef mx_h8 v8;
+    typedef mx_h2 v2;
+    __device__ __forceinline__ static mx_f16 mma(v8 a, v8 b, mx_f16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+    }
+};
+template <>
+struct MxType<true> {
+    typedef mx_b8 v8;
+    typedef mx_b2 v2;
+    __device__ __forceinline__ static mx_f16 mma(v8 a, v8 b, mx_f16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+    }
+};
+
+// x = hi + lo in the 16-bit type (lo carries the rounding residual of hi),
+// converted two values at a time (packed conversions)
+template <bool BF>
+__device__ __forceinline__ void mx_split(const float (&x)[8], typename MxType<BF>::v8 &hi,
+                                         typename MxType<BF>::v8 &lo) {
+    typedef typename MxType<BF>::v2 V2;
+    V2 h[4], l[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const mx_f2 v = {x[2 * p], x[2 * p + 1]};
+        h[p] = __builtin_convertvector(v, V2);
+        const mx_f2 hf = __builtin_convertvector(h[p], mx_f2);
+        l[p] = __builtin_convertvector(v - hf, V2);
+    }
+    hi = __builtin_shufflevector(__builtin_shufflevector(h[0], h[1], 0, 1, 2, 3),
+                                 __builtin_shufflevector(h[2], h[3], 0, 1, 2, 3), 0, 1, 2, 3, 4,
+                                 5, 6, 7);
+    lo = __builtin_shufflevector(__builtin_shufflevector(l[0], l[1], 0, 1, 2, 3),
+                                 __builtin_shufflevector(l[2], l[3], 0, 1, 2, 3), 0, 1, 2, 3, 4,
+                                 5, 6, 7);
+}
+
+// D = A B for one 32-column tile: re/im are the lane's 8 inputs
+template <bool BF>
+__device__ __forceinline__ mx_f16 mx_dft16(const float (&re)[8], const float (&im)[8],
+                                           const typename MxType<BF>::v8 (&a)[4]) {
+    typedef MxType<BF> X;
+    typename X::v8 rh, rl, ih, il;
+    mx_split<BF>(re, rh, rl);
+    mx_split<BF>(im, ih, il);
+    mx_f16 d = {};
+    d = X::mma(a[0], rh, d);    // A_hi(real-input block) B_hi
+    d = X::mma(a[0], rl, d);    // A_hi B_lo
+    d = X::mma(a[1], rh, d);    // A_lo B_hi
+    d = X::mma(a[2], ih, d);    // imaginary-input block
+    d = X::mma(a[2], il, d);
+    d = X::mma(a[3], ih, d);
+    return d;
+}
+
+template <bool RECUR, bool BF>
+__global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmList dl) {
+    constexpr int M = 4096;
+    constexpr int PL = M + M / 16 + 1;              // LDS plane per polarisation (float2)
+    __shared__ float2 sh[2 * PL];
+    __shared__ float red[4];
+
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int ci = lw % a.inner;
+    const int rest = lw / a.inner;
+    const int dt = rest % a.ndt;
+    const int chunk = a.cg0 + (rest / a.ndt) * a.inner + ci;
+    const int c = chunk % a.nchan;
+    const int bs = chunk / a.nchan;
+    const int s = bs % a.nsub;
+    const int b = bs / a.nsub;
+
+    const int t_id = threadIdx.x;
+    const int w = t_id >> 6, l = t_id & 63;
+    const int col = l & 31, h = l >> 5;
+    int jb[2];
+    jb[0] = 64 * w + col;
+    jb[1] = jb[0] + 32;
+
+    // A = F/16 split into hi/lo: a[0..1] real-input block hi/lo, a[2..3] imaginary.
+    // Row i of A is ordered so that accumulator element v of a lane in half hl
+    // (row 8 (v/4) + 4 hl + v % 4) holds the real (v even) or imaginary (v odd)
+    // part of output r = 8 hl + v/2: each (Re, Im) pair is two adjacent registers.
+    typename MxType<BF>::v8 amat[4];
+    {
+        const int i = l & 31;
+        const int vv = 4 * (i >> 3) + (i & 3);
+        const int r = 8 * ((i >> 2) & 1) + (vv >> 1);
+        const bool im_row = (vv & 1) != 0;
+        float re_blk[8], im_blk[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int q = 8 * h + t;
+            const float fr = cdmt::c16(r * q) * 0.0625f, fi = cdmt::s16(r * q) * 0.0625f;
+            re_blk[t] = im_row ? fi : fr;
+            im_blk[t] = im_row ? fr : -fi;
+        }
+        mx_split<BF>(re_blk, amat[0], amat[1]);
+        mx_split<BF>(im_blk, amat[2], amat[3]);
+    }
+
+    // this lane's bins: transform inputs q = 8h + t of butterflies j_b, i.e.
+    // spectrum bins (after the swap of halves) i = j_b + 256 ((8h + t) ^ 8)
+    cpair raw[2][8];
+    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            raw[bb][t] = src[jb[bb] + 256 * ((8 * h + t) ^ 8)];
+
+    // per-chunk power-of-two scale: max component -> about 2^14
+    float mx = 0.f;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(raw[bb][t].x), fabsf(raw[bb][t].y)),
+                                 fmaxf(fabsf(raw[bb][t].z), fabsf(raw[bb][t].w))));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        mx = fmaxf(mx, __shfl_xor(mx, o));
+    if (l == 0)
+        red[w] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    int ex = 0;
+    if (mx > 0.f) {
+        ex = 14 - ilogbf(mx);
+        ex = ex > 60 ? 60 : (ex < -60 ? -60 : ex);
+    }
+    const float up = ldexpf(1.0f, ex);
+    // |y|^2 = |y_computed|^2 * 16^6 * 2^(-2 ex)
+    const float down = ldexpf(1.0f, 24 - 2 * ex);
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            raw[bb][t] = cdmt::pscale(raw[bb][t], up);
+
+    // DM-independent part of Eq. 1 per bin, as in fused_dedisperse
+    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
+    double nu0, off;
+    if (a.chirp_ref == 0) {
+        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
+        off = -0.5 * M;
+    } else {
+        nu0 = fs;
+        off = (double)c * M - 0.5 * a.n;
+    }
+    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
+    double g2[2][8];
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int bin = jb[bb] + 256 * ((8 * h + t) ^ 8);
+            const double nu = ((double)bin + off) * a.delta;
+            g2[bb][t] = scale * nu * nu / (nu0 + nu);
+        }
+
+    const int d0 = dt * a.dm_tile;
+    const int d1 = min(a.ndm, d0 + a.dm_tile);
+    float2 step[2][8];
+    if constexpr (RECUR) {
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                raw[bb][t] = cdmt::pmul(raw[bb][t], cis_pi_f64(dl.dm[d0] * g2[bb][t]));
+                step[bb][t] = cis_pi_f64(a.dm_step * g2[bb][t]);
+            }
+    }
+
+    float *inten = reinterpret_cast<float *>(sh);
+    const int colo = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
+
+    typedef typename MxType<BF>::v8 V8;
+    for (int d = d0; d < d1; ++d) {
+        // B operands of the four tiles [butterfly][pol][re hi, re lo, im hi, im lo]
+        V8 bop[2][2][4];
+        auto set_ops = [&](int bb, const cpair (&x)[8]) {
+            float xr[8], xi[8], yr[8], yi[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                xr[t] = x[t].x;
+                xi[t] = x[t].y;
+                yr[t] = x[t].z;
+                yi[t] = x[t].w;
+            }
+            mx_split<BF>(xr, bop[bb][0][0], bop[bb][0][1]);
+            mx_split<BF>(xi, bop[bb][0][2], bop[bb][0][3]);
+            mx_split<BF>(yr, bop[bb][1][0], bop[bb][1][1]);
+            mx_split<BF>(yi, bop[bb][1][2], bop[bb][1][3]);
+        };
+        auto mma_tile = [&](int bb, int pol) {
+            typedef MxType<BF> X;
+            mx_f16 dd = {};
+            dd = X::mma(amat[0], bop[bb][pol][0], dd);   // A_hi B_hi, real inputs
+            dd = X::mma(amat[0], bop[bb][pol][1], dd);   // A_hi B_lo
+            dd = X::mma(amat[1], bop[bb][pol][0], dd);   // A_lo B_hi
+            dd = X::mma(amat[2], bop[bb][pol][2], dd);   // imaginary inputs
+            dd = X::mma(amat[2], bop[bb][pol][3], dd);
+            dd = X::mma(amat[3], bop[bb][pol][2], dd);
+            return dd;
+        };
+
+        // stage-0 inputs: the chirped spectrum
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+            if constexpr (RECUR) {
+                set_ops(bb, raw[bb]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    raw[bb][t] = cdmt::pmul(raw[bb][t], step[bb][t]);
+            } else {
+                cpair x[8];
+                const double dm = dl.dm[d];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const double tt = dm * g2[bb][t];
+                    const double n = rint(tt);
+                    float sn, cs;
+                    sincos_pi(static_cast<float>(tt - n), sn, cs);
+                    const int flip = static_cast<int>(n) << 31;
+                    sn = __int_as_float(__float_as_int(sn) ^ flip);
+                    cs = __int_as_float(__float_as_int(cs) ^ flip);
+                    x[t] = cdmt::pmul(raw[bb][t], make_float2(cs, sn));
+                }
+                set_ops(bb, x);
+            }
+        }
+
+#pragma unroll
+        for (int stage = 0; stage < 3; ++stage) {
+            const int ns = stage == 0 ? 1 : (stage == 1 ? 16 : 256);
+            if (stage > 0) {
+                // inputs of this stage from LDS, times the stage's twiddles
+                const float2 *tab = cdmt::stage_table<16>(16 * ns);
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    const int k = jb[bb] & (ns - 1);
+                    const float4 *row = reinterpret_cast<const float4 *>(tab + k * 16 + 8 * h);
+                    cpair x[8];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float4 tw = row[u];
+#pragma unroll
+                        for (int z = 0; z < 2; ++z) {
+                            const int t = 2 * u + z;
+                            const int e = jb[bb] + 256 * (8 * h + t);
+                            const float2 xx = sh[e + (e >> 4)];
+                            const float2 yy = sh[PL + e + (e >> 4)];
+                            x[t] = cdmt::pmul(make_float4(xx.x, xx.y, yy.x, yy.y),
+                                              z ? make_float2(tw.z, tw.w) : make_float2(tw.x, tw.y));
+                        }
+                    }
+                    set_ops(bb, x);
+                }
+                __syncthreads();      // every lane has read this stage's inputs
+            }
+            if (stage < 2) {
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    const int j = jb[bb];
+                    const int base = (j / ns) * ns * 16 + (j & (ns - 1));
+#pragma unroll
+                    for (int pol = 0; pol < 2; ++pol) {
+                        const mx_f16 dd = mma_tile(bb, pol);
+                        float2 *plane = sh + pol * PL;
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) {
+                            const int e = base + (8 * h + u) * ns;   // Stockham output index
+                            plane[e + (e >> 4)] = make_float2(dd[2 * u], dd[2 * u + 1]);
+                        }
+                    }
+                }
+                __syncthreads();
+            } else {
+                // last stage: detect each butterfly's outputs (sample m = j + 256 r);
+                // every lane has finished reading, so the intensity may overwrite LDS
+#pragma unroll
+                for (int bb = 0; bb < 2; ++bb) {
+                    const mx_f16 dx = mma_tile(bb, 0);
+                    const mx_f16 dy = mma_tile(bb, 1);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float re0 = dx[2 * u], im0 = dx[2 * u + 1];
+                        const float re1 = dy[2 * u], im1 = dy[2 * u + 1];
+                        inten[jb[bb] + 256 * (8 * h + u)] =
+                            (re0 * re0 + im0 * im0 + re1 * re1 + im1 * im1) * down;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        {
+            float *o = a.out + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + colo;
+            for (int tq = t_id; tq < a.tblk; tq += 256) {
+                const float *p = inten + a.nd_half + tq * a.ndec;
+                float acc = 0.f;
+                for (int q = 0; q < a.ndec; ++q)
+                    acc += p[q];
+                o[(long long)tq * a.nch_out] = acc;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 std::mutex g_init_mu;
@@ -514,10 +859,11 @@ bool arithmetic(const double *dm, int n, double tol) {
 // A dispatch covers at most 2^32 - 1 work-items, so large jobs are split into
 // several launches: by DM (at most kMaxDmPerLaunch per launch, passed by
 // value) and, when the grid would still be too large, by chunk groups.
-template <int M, int R>
+// MX = 0: FP32 vector path; 1: BF16x3 and 2: FP16x3 matrix-core path (M = 4096)
+template <int M, int R, int MX = 0>
 int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t st) {
-    constexpr int WG = FusedShape<M, R>::WG;
-    constexpr int C = FusedShape<M, R>::C;
+    constexpr int WG = MX ? 256 : FusedShape<M, R>::WG;
+    constexpr int C = MX ? 1 : FusedShape<M, R>::C;
     constexpr long long kMaxGroups = 0xffffffffLL / WG;
     const long long ncg = (a0.nchunks + C - 1) / C;
     const int inner = a0.nchan >= C ? a0.nchan / C : 1;
@@ -541,10 +887,20 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
         for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
             const long long n = ncg - cg0 < per ? ncg - cg0 : per;
             a.cg0 = (int)cg0;
-            if (recur)
-                fused_dedisperse<M, R, true><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
-            else
-                fused_dedisperse<M, R, false><<<(int)(n * a.ndt), WG, 0, st>>>(a, dl);
+            const int grid = (int)(n * a.ndt);
+            if constexpr (MX != 0) {
+                static_assert(M == 4096, "matrix-core path is built for M = 4096");
+                constexpr bool BF = MX == 1;
+                if (recur)
+                    fused_dedisperse_mx<true, BF><<<grid, WG, 0, st>>>(a, dl);
+                else
+                    fused_dedisperse_mx<false, BF><<<grid, WG, 0, st>>>(a, dl);
+            } else {
+                if (recur)
+                    fused_dedisperse<M, R, true><<<grid, WG, 0, st>>>(a, dl);
+                else
+                    fused_dedisperse<M, R, false><<<grid, WG, 0, st>>>(a, dl);
+            }
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
         }
@@ -586,8 +942,13 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
     case 1024: return launch_fused_m<1024, 16>(a, dms, ndm, st);
     case 2048: return r8 ? launch_fused_m<2048, 8>(a, dms, ndm, st)
                          : launch_fused_m<2048, 16>(a, dms, ndm, st);
-    case 4096: return r8 ? launch_fused_m<4096, 8>(a, dms, ndm, st)
-                         : launch_fused_m<4096, 16>(a, dms, ndm, st);
+    case 4096:
+        if (p->precision == 1)
+            return launch_fused_m<4096, 16, 1>(a, dms, ndm, st);
+        if (p->precision == 2)
+            return launch_fused_m<4096, 16, 2>(a, dms, ndm, st);
+        return r8 ? launch_fused_m<4096, 8>(a, dms, ndm, st)
+                  : launch_fused_m<4096, 16>(a, dms, ndm, st);
     case 8192: return launch_fused_m<8192, 16>(a, dms, ndm, st);
     default: return CDMT_E_UNSUPPORTED;
     }
@@ -683,7 +1044,7 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
     case CDMT_OPT_PRECISION:
         if (value < 0 || value > 2)
             return CDMT_E_ARG;
-        if (value != 0)
+        if (value != 0 && p->m != 4096)
             return CDMT_E_UNSUPPORTED;
         p->precision = value;
         return CDMT_OK;
