@@ -423,6 +423,19 @@ struct MxType<true> {
     }
 };
 
+// lo = f16(x - hi) for a pair (x0, x1) whose f16 parts are packed in hi:
+// FP32 fused multiply-add with an FP16 operand, result rounded into one half
+// of the destination (v_fma_mixlo_f16 / v_fma_mixhi_f16); x - hi is exact.
+__device__ __forceinline__ mx_h2 mx_residual_f16(mx_h2 hi, float x0, float x1) {
+    unsigned r;
+    const unsigned hb = __builtin_bit_cast(unsigned, hi);
+    asm volatile("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]"
+                 : "=v"(r) : "v"(hb), "v"(x0));
+    asm volatile("v_fma_mixhi_f16 %0, %1, -1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+                 : "+v"(r) : "v"(hb), "v"(x1));
+    return __builtin_bit_cast(mx_h2, r);
+}
+
 // x = hi + lo in the 16-bit type (lo carries the rounding residual of hi),
 // converted two values at a time (packed conversions)
 template <bool BF>
@@ -434,8 +447,12 @@ __device__ __forceinline__ void mx_split(const float (&x)[8], typename MxType<BF
     for (int p = 0; p < 4; ++p) {
         const mx_f2 v = {x[2 * p], x[2 * p + 1]};
         h[p] = __builtin_convertvector(v, V2);
-        const mx_f2 hf = __builtin_convertvector(h[p], mx_f2);
-        l[p] = __builtin_convertvector(v - hf, V2);
+        if constexpr (BF) {
+            const mx_f2 hf = __builtin_convertvector(h[p], mx_f2);
+            l[p] = __builtin_convertvector(v - hf, V2);
+        } else {
+            l[p] = mx_residual_f16(h[p], x[2 * p], x[2 * p + 1]);
+        }
     }
     hi = __builtin_shufflevector(__builtin_shufflevector(h[0], h[1], 0, 1, 2, 3),
                                  __builtin_shufflevector(h[2], h[3], 0, 1, 2, 3), 0, 1, 2, 3, 4,
@@ -603,16 +620,24 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
             mx_split<BF>(yr, bop[bb][1][0], bop[bb][1][1]);
             mx_split<BF>(yi, bop[bb][1][2], bop[bb][1][3]);
         };
-        auto mma_tile = [&](int bb, int pol) {
+        // both polarisations of butterfly bb, the two accumulation chains
+        // interleaved so consecutive matrix instructions are independent
+        auto mma_pair = [&](int bb, mx_f16 &dx, mx_f16 &dy) {
             typedef MxType<BF> X;
-            mx_f16 dd = {};
-            dd = X::mma(amat[0], bop[bb][pol][0], dd);   // A_hi B_hi, real inputs
-            dd = X::mma(amat[0], bop[bb][pol][1], dd);   // A_hi B_lo
-            dd = X::mma(amat[1], bop[bb][pol][0], dd);   // A_lo B_hi
-            dd = X::mma(amat[2], bop[bb][pol][2], dd);   // imaginary inputs
-            dd = X::mma(amat[2], bop[bb][pol][3], dd);
-            dd = X::mma(amat[3], bop[bb][pol][2], dd);
-            return dd;
+            dx = mx_f16{};
+            dy = mx_f16{};
+            dx = X::mma(amat[0], bop[bb][0][0], dx);   // A_hi B_hi, real inputs
+            dy = X::mma(amat[0], bop[bb][1][0], dy);
+            dx = X::mma(amat[0], bop[bb][0][1], dx);   // A_hi B_lo
+            dy = X::mma(amat[0], bop[bb][1][1], dy);
+            dx = X::mma(amat[1], bop[bb][0][0], dx);   // A_lo B_hi
+            dy = X::mma(amat[1], bop[bb][1][0], dy);
+            dx = X::mma(amat[2], bop[bb][0][2], dx);   // imaginary inputs
+            dy = X::mma(amat[2], bop[bb][1][2], dy);
+            dx = X::mma(amat[2], bop[bb][0][3], dx);
+            dy = X::mma(amat[2], bop[bb][1][3], dy);
+            dx = X::mma(amat[3], bop[bb][0][2], dx);
+            dy = X::mma(amat[3], bop[bb][1][2], dy);
         };
 
         // stage-0 inputs: the chirped spectrum
@@ -641,9 +666,10 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
             }
         }
 
-#pragma unroll
+#pragma unroll 1
         for (int stage = 0; stage < 3; ++stage) {
-            const int ns = stage == 0 ? 1 : (stage == 1 ? 16 : 256);
+            const int lg = 4 * stage;                 // log2 of ns
+            const int ns = 1 << lg;
             if (stage > 0) {
                 // inputs of this stage from LDS, times the stage's twiddles
                 const float2 *tab = cdmt::stage_table<16>(16 * ns);
@@ -673,16 +699,14 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
 #pragma unroll
                 for (int bb = 0; bb < 2; ++bb) {
                     const int j = jb[bb];
-                    const int base = (j / ns) * ns * 16 + (j & (ns - 1));
+                    const int base = ((j >> lg) << (lg + 4)) + (j & (ns - 1));
+                    mx_f16 dx, dy;
+                    mma_pair(bb, dx, dy);
 #pragma unroll
-                    for (int pol = 0; pol < 2; ++pol) {
-                        const mx_f16 dd = mma_tile(bb, pol);
-                        float2 *plane = sh + pol * PL;
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) {
-                            const int e = base + (8 * h + u) * ns;   // Stockham output index
-                            plane[e + (e >> 4)] = make_float2(dd[2 * u], dd[2 * u + 1]);
-                        }
+                    for (int u = 0; u < 8; ++u) {
+                        const int e = base + ((8 * h + u) << lg);   // Stockham output index
+                        sh[e + (e >> 4)] = make_float2(dx[2 * u], dx[2 * u + 1]);
+                        sh[PL + e + (e >> 4)] = make_float2(dy[2 * u], dy[2 * u + 1]);
                     }
                 }
                 __syncthreads();
@@ -691,8 +715,8 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
                 // every lane has finished reading, so the intensity may overwrite LDS
 #pragma unroll
                 for (int bb = 0; bb < 2; ++bb) {
-                    const mx_f16 dx = mma_tile(bb, 0);
-                    const mx_f16 dy = mma_tile(bb, 1);
+                    mx_f16 dx, dy;
+                    mma_pair(bb, dx, dy);
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
                         const float re0 = dx[2 * u], im0 = dx[2 * u + 1];
@@ -706,12 +730,25 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
         __syncthreads();
         {
             float *o = a.out + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + colo;
-            for (int tq = t_id; tq < a.tblk; tq += 256) {
-                const float *p = inten + a.nd_half + tq * a.ndec;
-                float acc = 0.f;
-                for (int q = 0; q < a.ndec; ++q)
-                    acc += p[q];
-                o[(long long)tq * a.nch_out] = acc;
+            if (((a.ndec | a.nd_half) & 3) == 0) {
+                const int n4 = a.ndec >> 2;
+                for (int tq = t_id; tq < a.tblk; tq += 256) {
+                    const float4 *p = reinterpret_cast<const float4 *>(inten + a.nd_half) + tq * n4;
+                    float acc = 0.f;
+                    for (int q = 0; q < n4; ++q) {
+                        const float4 x = p[q];
+                        acc += (x.x + x.y) + (x.z + x.w);
+                    }
+                    o[(long long)tq * a.nch_out] = acc;
+                }
+            } else {
+                for (int tq = t_id; tq < a.tblk; tq += 256) {
+                    const float *p = inten + a.nd_half + tq * a.ndec;
+                    float acc = 0.f;
+                    for (int q = 0; q < a.ndec; ++q)
+                        acc += p[q];
+                    o[(long long)tq * a.nch_out] = acc;
+                }
             }
         }
         __syncthreads();
