@@ -206,6 +206,21 @@ __device__ __forceinline__ float2 cis_pi_f64(double t) {
     return make_float2(cs, sn);
 }
 
+// a *= w for both complex values of a pair, in place: the cross products are
+// formed from the old values first, then each fused multiply-add overwrites
+// its own input (tied operands), so a value carried around a loop keeps its
+// registers instead of being copied back at the loop latch.
+__device__ __forceinline__ void pmul_inplace(cpair &a, float2 w) {
+    float xr = a.x, xi = a.y, yr = a.z, yi = a.w;
+    const float tx = xi * w.y, ux = xr * w.y;
+    const float ty = yi * w.y, uy = yr * w.y;
+    asm("v_fma_f32 %0, %0, %1, -%2" : "+v"(xr) : "v"(w.x), "v"(tx));
+    asm("v_fma_f32 %0, %0, %1, %2" : "+v"(xi) : "v"(w.x), "v"(ux));
+    asm("v_fma_f32 %0, %0, %1, -%2" : "+v"(yr) : "v"(w.x), "v"(ty));
+    asm("v_fma_f32 %0, %0, %1, %2" : "+v"(yi) : "v"(w.x), "v"(uy));
+    a = make_float4(xr, xi, yr, yi);
+}
+
 struct FusedArgs {
     const cpair *spec;      // [block][subband][N]
     float *out;             // first DM of this launch: [ndm][ntime_out][nsub*nchan]
@@ -301,6 +316,10 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
     const int d0 = dt * a.dm_tile;
     const int d1 = min(a.ndm, d0 + a.dm_tile);
 
+    // Where the next DM's spectrum is formed: after the transform, in place
+    // (saves the register copies of a loop-carried product), or before it
+    // where the in-place form costs spills (larger M, 8 bins per lane).
+    constexpr bool kLateStep = (R == 16 && M <= 4096);
     float2 step[R];
     if constexpr (RECUR) {
         // P(d0) = raw exp(i pi dm(d0) g2) and the per-DM step, in double
@@ -316,9 +335,9 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
         if constexpr (RECUR) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                // swap halves per channel: bin i -> transform input (i + M/2) mod M
-                v[q ^ (R / 2)] = raw[q];
-                raw[q] = cdmt::pmul(raw[q], step[q]);
+                v[q ^ (R / 2)] = raw[q];     // swap halves per channel (see below)
+                if constexpr (!kLateStep)
+                    raw[q] = cdmt::pmul(raw[q], step[q]);
             }
         } else {
             const double dm = dl.dm[d];
@@ -337,6 +356,12 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
             }
         }
         cdmt::wg_fft<M, +1>(v, tt, lds);
+        if constexpr (RECUR && kLateStep) {
+            // advance to the next DM once the transform has consumed raw
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+                pmul_inplace(raw[q], step[q]);
+        }
 
         // detect; channel sample m = tt + T q
 #pragma unroll
@@ -602,130 +627,187 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
     float *inten = reinterpret_cast<float *>(sh);
     const int colo = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
 
-    typedef typename MxType<BF>::v8 V8;
-    for (int d = d0; d < d1; ++d) {
-        // B operands of the four tiles [butterfly][pol][re hi, re lo, im hi, im lo]
-        V8 bop[2][2][4];
-        auto set_ops = [&](int bb, const cpair (&x)[8]) {
-            float xr[8], xi[8], yr[8], yi[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                xr[t] = x[t].x;
-                xi[t] = x[t].y;
-                yr[t] = x[t].z;
-                yi[t] = x[t].w;
-            }
-            mx_split<BF>(xr, bop[bb][0][0], bop[bb][0][1]);
-            mx_split<BF>(xi, bop[bb][0][2], bop[bb][0][3]);
-            mx_split<BF>(yr, bop[bb][1][0], bop[bb][1][1]);
-            mx_split<BF>(yi, bop[bb][1][2], bop[bb][1][3]);
-        };
-        // both polarisations of butterfly bb, the two accumulation chains
-        // interleaved so consecutive matrix instructions are independent
-        auto mma_pair = [&](int bb, mx_f16 &dx, mx_f16 &dy) {
-            typedef MxType<BF> X;
-            dx = mx_f16{};
-            dy = mx_f16{};
-            dx = X::mma(amat[0], bop[bb][0][0], dx);   // A_hi B_hi, real inputs
-            dy = X::mma(amat[0], bop[bb][1][0], dy);
-            dx = X::mma(amat[0], bop[bb][0][1], dx);   // A_hi B_lo
-            dy = X::mma(amat[0], bop[bb][1][1], dy);
-            dx = X::mma(amat[1], bop[bb][0][0], dx);   // A_lo B_hi
-            dy = X::mma(amat[1], bop[bb][1][0], dy);
-            dx = X::mma(amat[2], bop[bb][0][2], dx);   // imaginary inputs
-            dy = X::mma(amat[2], bop[bb][1][2], dy);
-            dx = X::mma(amat[2], bop[bb][0][3], dx);
-            dy = X::mma(amat[2], bop[bb][1][3], dy);
-            dx = X::mma(amat[3], bop[bb][0][2], dx);
-            dy = X::mma(amat[3], bop[bb][1][2], dy);
-        };
+    // LDS addresses (float2 index, before the pol-Y plane offset PL) of this
+    // lane's tile 0; tile 1 (butterfly j + 32) adds a constant.  With the
+    // padding e + e/16 the Stockham indices reduce to:
+    //   stage-0 outputs   e = 16 j + r                 -> 17 j + r
+    //   stage-1 outputs   e = 256 (j/16) + j%16 + 16 r -> 272 (j/16) + j%16 + 17 r
+    //   stage-1/2 inputs  e = j + 256 q                -> j + j/16 + 272 q
+    // with r = 8h + u, q = 8h + t.
+    const int j0 = jb[0];
+    const int wr0 = 17 * j0 + 8 * h;                          // + u, tile 1: + 544
+    const int wr1 = 272 * (j0 >> 4) + (j0 & 15) + 136 * h;    // + 17 u, tile 1: + 544
+    const int rd = j0 + (j0 >> 4) + 2176 * h;                 // + 272 t, tile 1: + 34
+    // stage-1 twiddle row k = j % 16 is the same for both tiles; stage 2: k = j
+    const float4 *tw1p =
+        reinterpret_cast<const float4 *>(cdmt::stage_table<16>(256) + (j0 & 15) * 16 + 8 * h);
+    const float4 *tw2p =
+        reinterpret_cast<const float4 *>(cdmt::stage_table<16>(4096) + j0 * 16 + 8 * h);
 
-        // stage-0 inputs: the chirped spectrum
+    typedef typename MxType<BF>::v8 V8;
+    typedef MxType<BF> X;
+    // B operands of one tile: [pol][re hi, re lo, im hi, im lo]; two sets so
+    // that one tile's matrix products overlap the other tile's conversions
+    V8 opa[2][4], opb[2][4];
+    auto split_tile = [&](V8 (&op)[2][4], const cpair (&x)[8]) {
+        float xr[8], xi[8], yr[8], yi[8];
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb) {
-            if constexpr (RECUR) {
-                set_ops(bb, raw[bb]);
+        for (int t = 0; t < 8; ++t) {
+            xr[t] = x[t].x;
+            xi[t] = x[t].y;
+            yr[t] = x[t].z;
+            yi[t] = x[t].w;
+        }
+        mx_split<BF>(xr, op[0][0], op[0][1]);
+        mx_split<BF>(xi, op[0][2], op[0][3]);
+        mx_split<BF>(yr, op[1][0], op[1][1]);
+        mx_split<BF>(yi, op[1][2], op[1][3]);
+    };
+    // both polarisations of one tile, the two accumulation chains interleaved
+    // so consecutive matrix instructions are independent
+    auto mma_tile = [&](const V8 (&op)[2][4], mx_f16 &dx, mx_f16 &dy) {
+        dx = mx_f16{};
+        dy = mx_f16{};
+        dx = X::mma(amat[0], op[0][0], dx);   // A_hi B_hi, real inputs
+        dy = X::mma(amat[0], op[1][0], dy);
+        dx = X::mma(amat[0], op[0][1], dx);   // A_hi B_lo
+        dy = X::mma(amat[0], op[1][1], dy);
+        dx = X::mma(amat[1], op[0][0], dx);   // A_lo B_hi
+        dy = X::mma(amat[1], op[1][0], dy);
+        dx = X::mma(amat[2], op[0][2], dx);   // imaginary inputs
+        dy = X::mma(amat[2], op[1][2], dy);
+        dx = X::mma(amat[2], op[0][3], dx);
+        dy = X::mma(amat[2], op[1][3], dy);
+        dx = X::mma(amat[3], op[0][2], dx);
+        dy = X::mma(amat[3], op[1][2], dy);
+    };
+    auto read_tile = [&](int base, cpair (&x)[8]) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    raw[bb][t] = cdmt::pmul(raw[bb][t], step[bb][t]);
-            } else {
-                cpair x[8];
-                const double dm = dl.dm[d];
+        for (int t = 0; t < 8; ++t) {
+            const float2 xx = sh[base + 272 * t];
+            const float2 yy = sh[PL + base + 272 * t];
+            x[t] = make_float4(xx.x, xx.y, yy.x, yy.y);
+        }
+    };
+    auto twiddle_tile = [&](cpair (&x)[8], const float4 (&tw)[4]) {
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const double tt = dm * g2[bb][t];
-                    const double n = rint(tt);
-                    float sn, cs;
-                    sincos_pi(static_cast<float>(tt - n), sn, cs);
-                    const int flip = static_cast<int>(n) << 31;
-                    sn = __int_as_float(__float_as_int(sn) ^ flip);
-                    cs = __int_as_float(__float_as_int(cs) ^ flip);
-                    x[t] = cdmt::pmul(raw[bb][t], make_float2(cs, sn));
-                }
-                set_ops(bb, x);
+        for (int u = 0; u < 4; ++u) {
+            x[2 * u] = cdmt::pmul(x[2 * u], make_float2(tw[u].x, tw[u].y));
+            x[2 * u + 1] = cdmt::pmul(x[2 * u + 1], make_float2(tw[u].z, tw[u].w));
+        }
+    };
+    auto load_tw = [&](const float4 *p, float4 (&tw)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            tw[u] = p[u];
+    };
+    // the chirped spectrum of tile bb for DM d (exact transfer function)
+    auto chirp_tile = [&](int bb, double dm, cpair (&x)[8]) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const double tt = dm * g2[bb][t];
+            const double n = rint(tt);
+            float sn, cs;
+            sincos_pi(static_cast<float>(tt - n), sn, cs);
+            const int flip = static_cast<int>(n) << 31;
+            sn = __int_as_float(__float_as_int(sn) ^ flip);
+            cs = __int_as_float(__float_as_int(cs) ^ flip);
+            x[t] = cdmt::pmul(raw[bb][t], make_float2(cs, sn));
+        }
+    };
+    auto detect_tile = [&](int j, const mx_f16 &dx, const mx_f16 &dy) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float re0 = dx[2 * u], im0 = dx[2 * u + 1];
+            const float re1 = dy[2 * u], im1 = dy[2 * u + 1];
+            inten[j + 256 * (8 * h + u)] = (re0 * re0 + im0 * im0 + re1 * re1 + im1 * im1) * down;
+        }
+    };
+
+    for (int d = d0; d < d1; ++d) {
+        mx_f16 dx, dy;
+        cpair x0[8], x1[8];
+        float4 tw1[4], tw2[4];
+
+        // stage 0: inputs are the chirped spectrum
+        if constexpr (RECUR) {
+            split_tile(opa, raw[0]);
+        } else {
+            chirp_tile(0, dl.dm[d], x0);
+            split_tile(opa, x0);
+        }
+        mma_tile(opa, dx, dy);
+        if constexpr (RECUR) {
+            split_tile(opb, raw[1]);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                pmul_inplace(raw[0][t], step[0][t]);
+        } else {
+            chirp_tile(1, dl.dm[d], x1);
+            split_tile(opb, x1);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sh[wr0 + u] = make_float2(dx[2 * u], dx[2 * u + 1]);
+            sh[PL + wr0 + u] = make_float2(dy[2 * u], dy[2 * u + 1]);
+        }
+        mma_tile(opb, dx, dy);
+        if constexpr (RECUR) {
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                pmul_inplace(raw[1][t], step[1][t]);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            sh[wr0 + 544 + u] = make_float2(dx[2 * u], dx[2 * u + 1]);
+            sh[PL + wr0 + 544 + u] = make_float2(dy[2 * u], dy[2 * u + 1]);
+        }
+        __syncthreads();
+
+        // stage 1
+        load_tw(tw1p, tw1);
+        read_tile(rd, x0);
+        read_tile(rd + 34, x1);
+        twiddle_tile(x0, tw1);
+        split_tile(opa, x0);
+        twiddle_tile(x1, tw1);
+        split_tile(opb, x1);
+        __syncthreads();
+        {
+            // tile 0's stores overlap tile 1's matrix products
+            mx_f16 ex, ey;
+            mma_tile(opa, dx, dy);
+            mma_tile(opb, ex, ey);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                sh[wr1 + 17 * u] = make_float2(dx[2 * u], dx[2 * u + 1]);
+                sh[PL + wr1 + 17 * u] = make_float2(dy[2 * u], dy[2 * u + 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                sh[wr1 + 544 + 17 * u] = make_float2(ex[2 * u], ex[2 * u + 1]);
+                sh[PL + wr1 + 544 + 17 * u] = make_float2(ey[2 * u], ey[2 * u + 1]);
             }
         }
+        __syncthreads();
 
-#pragma unroll 1
-        for (int stage = 0; stage < 3; ++stage) {
-            const int lg = 4 * stage;                 // log2 of ns
-            const int ns = 1 << lg;
-            if (stage > 0) {
-                // inputs of this stage from LDS, times the stage's twiddles
-                const float2 *tab = cdmt::stage_table<16>(16 * ns);
-#pragma unroll
-                for (int bb = 0; bb < 2; ++bb) {
-                    const int k = jb[bb] & (ns - 1);
-                    const float4 *row = reinterpret_cast<const float4 *>(tab + k * 16 + 8 * h);
-                    cpair x[8];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float4 tw = row[u];
-#pragma unroll
-                        for (int z = 0; z < 2; ++z) {
-                            const int t = 2 * u + z;
-                            const int e = jb[bb] + 256 * (8 * h + t);
-                            const float2 xx = sh[e + (e >> 4)];
-                            const float2 yy = sh[PL + e + (e >> 4)];
-                            x[t] = cdmt::pmul(make_float4(xx.x, xx.y, yy.x, yy.y),
-                                              z ? make_float2(tw.z, tw.w) : make_float2(tw.x, tw.y));
-                        }
-                    }
-                    set_ops(bb, x);
-                }
-                __syncthreads();      // every lane has read this stage's inputs
-            }
-            if (stage < 2) {
-#pragma unroll
-                for (int bb = 0; bb < 2; ++bb) {
-                    const int j = jb[bb];
-                    const int base = ((j >> lg) << (lg + 4)) + (j & (ns - 1));
-                    mx_f16 dx, dy;
-                    mma_pair(bb, dx, dy);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int e = base + ((8 * h + u) << lg);   // Stockham output index
-                        sh[e + (e >> 4)] = make_float2(dx[2 * u], dx[2 * u + 1]);
-                        sh[PL + e + (e >> 4)] = make_float2(dy[2 * u], dy[2 * u + 1]);
-                    }
-                }
-                __syncthreads();
-            } else {
-                // last stage: detect each butterfly's outputs (sample m = j + 256 r);
-                // every lane has finished reading, so the intensity may overwrite LDS
-#pragma unroll
-                for (int bb = 0; bb < 2; ++bb) {
-                    mx_f16 dx, dy;
-                    mma_pair(bb, dx, dy);
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const float re0 = dx[2 * u], im0 = dx[2 * u + 1];
-                        const float re1 = dy[2 * u], im1 = dy[2 * u + 1];
-                        inten[jb[bb] + 256 * (8 * h + u)] =
-                            (re0 * re0 + im0 * im0 + re1 * re1 + im1 * im1) * down;
-                    }
-                }
-            }
+        // stage 2, then detection into LDS (every lane has read its inputs)
+        load_tw(tw2p, tw2);
+        read_tile(rd, x0);
+        read_tile(rd + 34, x1);
+        twiddle_tile(x0, tw2);
+        load_tw(tw2p + 32 * 8, tw2);      // tile 1: row j + 32, 8 float4 a row
+        split_tile(opa, x0);
+        twiddle_tile(x1, tw2);
+        split_tile(opb, x1);
+        __syncthreads();
+        {
+            // tile 0's detection overlaps tile 1's matrix products
+            mx_f16 ex, ey;
+            mma_tile(opa, dx, dy);
+            mma_tile(opb, ex, ey);
+            detect_tile(j0, dx, dy);
+            detect_tile(j0 + 32, ex, ey);
         }
         __syncthreads();
         {
