@@ -35,6 +35,8 @@ VALU_FP32_PACKED_PEAK_TFLOPS = 2 * VALU_FP32_PEAK_TFLOPS
 
 
 PROFILE = os.path.join(ROOT, "profiles", "fused_dedisperse_lofar_hba_288sub_128dm.md")
+# dense FP16 / BF16 matrix-core peak of the MI355X (no sparsity)
+MFMA_F16_PEAK_TFLOPS = 2500.0
 
 
 def measured_traffic(kernel: str):
@@ -57,6 +59,14 @@ def measured_traffic(kernel: str):
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def mx_mfma_flops_per_chunk_dm() -> float:
+    """Matrix-core flops issued by the split-precision DM stage per channel
+    chunk of 4096 bins and DM: 3 radix-16 stages x 16 column tiles (256
+    butterflies x 2 pols / 32) x 6 products of 32x32x16 (hi.hi, hi.lo, lo.hi
+    for the real- and imaginary-input halves), 2 flops per product term."""
+    return 3 * 16 * 6 * (2 * 32 * 32 * 16)
 
 
 def fused_flops_per_bin(m: int) -> float:
@@ -272,6 +282,14 @@ def main():
             variants[name] = {"value": round(ndm * w.data_seconds * args.steps / (el + fwd_avg * args.steps), 2),
                               "fused_ms": round(ms, 3),
                               "normwise_vs_" + args.precision: rel}
+            if code != 0:
+                mflops = mx_mfma_flops_per_chunk_dm() * w.nblock * w.nsub * w.nchan * ndm
+                ach = mflops / (ms / 1e3) / 1e12
+                variants[name]["roofline"] = {
+                    "kernel": "fused_dedisperse_mx", "bound": "mfma", "achieved": round(ach, 1),
+                    "peak": MFMA_F16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / MFMA_F16_PEAK_TFLOPS, 4),
+                    "traffic": measured_traffic("fused_dedisperse_mx<%s>" % name)}
             outputs[name] = o2
             log(f"variant {name}: fused {ms:.3f} ms, normwise vs {args.precision} {rel:.2e}")
         cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, prec_code)

@@ -316,10 +316,6 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
     const int d0 = dt * a.dm_tile;
     const int d1 = min(a.ndm, d0 + a.dm_tile);
 
-    // Where the next DM's spectrum is formed: after the transform, in place
-    // (saves the register copies of a loop-carried product), or before it
-    // where the in-place form costs spills (larger M, 8 bins per lane).
-    constexpr bool kLateStep = (R == 16 && M <= 4096);
     float2 step[R];
     if constexpr (RECUR) {
         // P(d0) = raw exp(i pi dm(d0) g2) and the per-DM step, in double
@@ -335,9 +331,9 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
         if constexpr (RECUR) {
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                v[q ^ (R / 2)] = raw[q];     // swap halves per channel (see below)
-                if constexpr (!kLateStep)
-                    raw[q] = cdmt::pmul(raw[q], step[q]);
+                // swap halves per channel: bin i -> transform input (i + M/2) mod M
+                v[q ^ (R / 2)] = raw[q];
+                raw[q] = cdmt::pmul(raw[q], step[q]);
             }
         } else {
             const double dm = dl.dm[d];
@@ -356,12 +352,6 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
             }
         }
         cdmt::wg_fft<M, +1>(v, tt, lds);
-        if constexpr (RECUR && kLateStep) {
-            // advance to the next DM once the transform has consumed raw
-#pragma unroll
-            for (int q = 0; q < R; ++q)
-                pmul_inplace(raw[q], step[q]);
-        }
 
         // detect; channel sample m = tt + T q
 #pragma unroll
@@ -728,6 +718,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
         mx_f16 dx, dy;
         cpair x0[8], x1[8];
         float4 tw1[4], tw2[4];
+        load_tw(tw1p, tw1);               // stage 1's twiddles; latency covered by stage 0
 
         // stage 0: inputs are the chirped spectrum
         if constexpr (RECUR) {
@@ -765,7 +756,6 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
         __syncthreads();
 
         // stage 1
-        load_tw(tw1p, tw1);
         read_tile(rd, x0);
         read_tile(rd + 34, x1);
         twiddle_tile(x0, tw1);
@@ -778,6 +768,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
             mx_f16 ex, ey;
             mma_tile(opa, dx, dy);
             mma_tile(opb, ex, ey);
+            load_tw(tw2p, tw2);           // stage 2, tile 0: latency covered by the stores
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 sh[wr1 + 17 * u] = make_float2(dx[2 * u], dx[2 * u + 1]);
@@ -792,7 +783,6 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
         __syncthreads();
 
         // stage 2, then detection into LDS (every lane has read its inputs)
-        load_tw(tw2p, tw2);
         read_tile(rd, x0);
         read_tile(rd + 34, x1);
         twiddle_tile(x0, tw2);
