@@ -16,6 +16,7 @@ Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -139,6 +140,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the other DM-stage arithmetics (mixed vs FP32 plain)")
+    ap.add_argument("--redigitise", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the 8-bit redigitisation of the filterbank")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration for profiles)")
     args = ap.parse_args()
@@ -294,6 +297,31 @@ def main():
             log(f"variant {name}: fused {ms:.3f} ms, normwise vs {args.precision} {rel:.2e}")
         cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, prec_code)
         line["variants"] = variants
+    if args.redigitise:
+        # 8-bit redigitisation of the FP32 filterbank (the paper's step after the
+        # transpose), timed on its own: two reads of the filterbank, one byte write
+        rws = torch.empty(max(1, cdmt.cdmt_redigitise_workspace_size(ndm, ntout, nch)),
+                          dtype=torch.uint8, device=dev)
+        codes, rmean, rscale = cdmt.redigitise(out, 64.0, 16.0, workspace=rws)
+        torch.cuda.synchronize()
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+        for i in range(args.steps):
+            ev[i][0].record(stream)
+            cdmt.cdmt_redigitise(ctypes.c_void_p(out.data_ptr()), ndm, ntout, nch, 64.0, 16.0,
+                                 ctypes.c_void_p(rws.data_ptr()), rws.numel(),
+                                 ctypes.c_void_p(codes.data_ptr()),
+                                 ctypes.c_void_p(rmean.data_ptr()),
+                                 ctypes.c_void_p(rscale.data_ptr()),
+                                 ctypes.c_void_p(stream.cuda_stream))
+            ev[i][1].record(stream)
+        torch.cuda.synchronize()
+        rms = sum(e[0].elapsed_time(e[1]) for e in ev) / args.steps
+        rbytes = 2 * out.numel() * 4 + out.numel() + 2 * rws.numel()
+        line["redigitise"] = {"ms": round(rms, 3), "bound": "hbm",
+                              "algorithmic_GBs": round(rbytes / rms / 1e6, 1),
+                              "hbm_frac": round(rbytes / rms / 1e6 / HBM_PEAK_GBS, 4)}
+        log(f"redigitise: {rms:.3f} ms")
+        del codes, rws
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads")

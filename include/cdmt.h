@@ -145,6 +145,33 @@ int cdmt_dedisperse_spectra(cdmt_plan_t plan, void *workspace, size_t ws_bytes, 
 int cdmt_dedisperse(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const void *voltages,
                     int nblock, const double *dm_list, int ndm, float *out, void *hip_stream);
 
+/*
+ * Redigitisation of a filterbank to 8-bit codes (Sec. 3, the paragraph after
+ * the transpose; Alg. 1 "redigitize").  Independent of any plan: it takes any
+ * FP32 filterbank [ndm][ntime][nchan], e.g. the output of cdmt_dedisperse.
+ * For every DM trial d and channel c, over the ntime samples of the call:
+ *   mean[d][c]  = (float) mu,  mu = average of the series (FP64)
+ *   scale[d][c] = (float) (counts_per_sigma / sigma), sigma = population
+ *                 standard deviation (FP64); 0 when sigma = 0
+ *   codes[d][t][c] = clamp(rint((x - mean) * scale + zero), 0, 255), each of
+ *                 the three FP32 operations rounded separately, rint rounding
+ *                 half to even.
+ * zero is the code given to the mean and counts_per_sigma the codes per
+ * standard deviation (finite, > 0); x ~= (code - zero) / scale + mean.
+ *   filterbank  device float32 [ndm][ntime][nchan] (finite values)
+ *   codes       device uint8 [ndm][ntime][nchan]
+ *   mean, scale device float32 [ndm][nchan]
+ *   workspace   device, at least cdmt_redigitise_workspace_size bytes
+ *               (per-segment partial moments, 16 B per 1024 samples per
+ *               DM and channel)
+ * ndm = 0 is a no-op.  ndm and ceil(ntime / 1024) must not exceed 65535
+ * (CDMT_E_SHAPE).  Asynchronous on hip_stream; on error nothing is written.
+ */
+int cdmt_redigitise_workspace_size(int ndm, long long ntime, int nchan, size_t *bytes);
+int cdmt_redigitise(const float *filterbank, int ndm, long long ntime, int nchan, float zero,
+                    float counts_per_sigma, void *workspace, size_t ws_bytes,
+                    unsigned char *codes, float *mean, float *scale, void *hip_stream);
+
 /* Free a plan (NULL is accepted). */
 void cdmt_destroy(cdmt_plan_t plan);
 

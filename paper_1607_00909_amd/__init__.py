@@ -30,7 +30,8 @@ CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
 # every symbol include/cdmt.h declares
 EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
            "cdmt_output_shape", "cdmt_workspace_size", "cdmt_forward",
-           "cdmt_dedisperse_spectra", "cdmt_dedisperse", "cdmt_destroy", "cdmt_status_string")
+           "cdmt_dedisperse_spectra", "cdmt_dedisperse", "cdmt_destroy", "cdmt_status_string",
+           "cdmt_redigitise_workspace_size", "cdmt_redigitise")
 
 _lib = None
 _lock = threading.Lock()
@@ -72,6 +73,9 @@ def load():
         lib.cdmt_destroy.restype = None
         lib.cdmt_status_string.argtypes = [I]
         lib.cdmt_status_string.restype = ctypes.c_char_p
+        F = ctypes.c_float
+        lib.cdmt_redigitise_workspace_size.argtypes = [I, LL, I, ctypes.POINTER(Z)]
+        lib.cdmt_redigitise.argtypes = [P, I, LL, I, F, F, P, Z, P, P, P, P]
         for name in EXPORTS:
             if not hasattr(lib, name):
                 raise RuntimeError(f"{LIB_PATH} does not export {name}")
@@ -152,6 +156,44 @@ def cdmt_dedisperse(plan, workspace, ws_bytes, voltages, nblock, dms, out, strea
 def cdmt_destroy(plan) -> None:
     if plan:
         load().cdmt_destroy(plan)
+
+
+def cdmt_redigitise_workspace_size(ndm, ntime, nchan) -> int:
+    v = ctypes.c_size_t()
+    _check(load().cdmt_redigitise_workspace_size(ndm, ntime, nchan, ctypes.byref(v)),
+           "cdmt_redigitise_workspace_size")
+    return v.value
+
+
+def cdmt_redigitise(filterbank, ndm, ntime, nchan, zero, counts_per_sigma, workspace, ws_bytes,
+                    codes, mean, scale, stream) -> None:
+    _check(load().cdmt_redigitise(filterbank, ndm, ntime, nchan, zero, counts_per_sigma,
+                                  workspace, ws_bytes, codes, mean, scale, stream),
+           "cdmt_redigitise")
+
+
+def redigitise(fb, zero=64.0, counts_per_sigma=16.0, workspace=None, stream=None):
+    """8-bit codes of a device filterbank fb [ndm][ntime][nchan] float32:
+    returns (codes uint8, mean float32 [ndm][nchan], scale float32 [ndm][nchan])."""
+    import torch
+    if fb.dtype != torch.float32 or not fb.is_cuda or not fb.is_contiguous() or fb.dim() != 3:
+        raise ValueError("filterbank must be a contiguous float32 [ndm][ntime][nchan] device tensor")
+    ndm, ntime, nchan = (int(v) for v in fb.shape)
+    codes = torch.empty(fb.shape, dtype=torch.uint8, device=fb.device)
+    mean = torch.empty((ndm, nchan), dtype=torch.float32, device=fb.device)
+    scale = torch.empty((ndm, nchan), dtype=torch.float32, device=fb.device)
+    if ndm == 0:
+        return codes, mean, scale
+    if workspace is None:
+        workspace = torch.empty(max(1, cdmt_redigitise_workspace_size(ndm, ntime, nchan)),
+                                dtype=torch.uint8, device=fb.device)
+    s = stream if stream is not None else torch.cuda.current_stream()
+    cdmt_redigitise(ctypes.c_void_p(fb.data_ptr()), ndm, ntime, nchan, float(zero),
+                    float(counts_per_sigma), ctypes.c_void_p(workspace.data_ptr()),
+                    workspace.numel(), ctypes.c_void_p(codes.data_ptr()),
+                    ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(scale.data_ptr()),
+                    ctypes.c_void_p(s.cuda_stream))
+    return codes, mean, scale
 
 
 # ------------------------------------------------- torch-facing wrapper ----
@@ -237,4 +279,4 @@ def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
 
 
 __all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
-                                                          "dm_seconds", "EXPORTS"]
+                                                          "dm_seconds", "redigitise", "EXPORTS"]

@@ -10,8 +10,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = os.path.join(HERE, "csrc", "cdmt.hip")
-DEPS = [SRC, os.path.join(HERE, "csrc", "fft_core.hpp"), os.path.join(ROOT, "include", "cdmt.h")]
+SRCS = [os.path.join(HERE, "csrc", "cdmt.hip"), os.path.join(HERE, "csrc", "redigit.hip")]
+DEPS = [*SRCS, os.path.join(HERE, "csrc", "fft_core.hpp"), os.path.join(ROOT, "include", "cdmt.h")]
 LIB = os.path.join(HERE, "libcdmt.so")
 ARCH = os.environ.get("CDMT_OFFLOAD_ARCH", "gfx950")
 
@@ -32,7 +32,7 @@ def hipcc() -> str:
 
 def build(verbose: bool = False, save_temps: str | None = None) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), SRC, "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), *SRCS, "-o", tmp]
     if save_temps:
         cmd.insert(1, f"-save-temps={save_temps}")
     if verbose:

@@ -163,3 +163,35 @@ def test_noop_calls_touch_nothing(lib):
         assert lib.cdmt_forward(None, None, 0, None, 1, None) == cdmt.CDMT_E_ARG
     finally:
         cdmt.cdmt_destroy(p)
+
+
+def test_redigitise_validation(lib):
+    """Workspace formula and the error paths of cdmt_redigitise, all returned
+    before any device work."""
+    import ctypes
+    z = ctypes.c_size_t()
+    assert lib.cdmt_redigitise_workspace_size(3, 2049, 10, ctypes.byref(z)) == cdmt.CDMT_OK
+    assert z.value == 3 * 3 * 10 * 16          # ceil(2049 / 1024) segments x (mean, M2) FP64
+    assert lib.cdmt_redigitise_workspace_size(0, 1, 1, ctypes.byref(z)) == cdmt.CDMT_OK
+    assert z.value == 0
+    for args in ((-1, 1, 1), (1, 0, 1), (1, 1, 0)):
+        assert lib.cdmt_redigitise_workspace_size(*args, ctypes.byref(z)) == cdmt.CDMT_E_ARG
+    P = ctypes.c_void_p(16)
+    call = lib.cdmt_redigitise
+    # ndm = 0: no-op, whatever the pointers
+    assert call(None, 0, 5, 4, 64.0, 16.0, None, 0, None, None, None, None) == cdmt.CDMT_OK
+    # bad shapes and parameters
+    assert call(P, 1, 0, 4, 64.0, 16.0, P, 1 << 30, P, P, P, None) == cdmt.CDMT_E_ARG
+    assert call(P, 1, 5, 0, 64.0, 16.0, P, 1 << 30, P, P, P, None) == cdmt.CDMT_E_ARG
+    assert call(P, 1, 5, 4, float("nan"), 16.0, P, 1 << 30, P, P, P, None) == cdmt.CDMT_E_ARG
+    assert call(P, 1, 5, 4, 64.0, 0.0, P, 1 << 30, P, P, P, None) == cdmt.CDMT_E_ARG
+    assert call(P, 1, 5, 4, 64.0, float("inf"), P, 1 << 30, P, P, P, None) == cdmt.CDMT_E_ARG
+    assert call(None, 1, 5, 4, 64.0, 16.0, P, 1 << 30, P, P, P, None) == cdmt.CDMT_E_ARG
+    assert call(P, 1, 5, 4, 64.0, 16.0, P, 1 << 30, None, P, P, None) == cdmt.CDMT_E_ARG
+    # too many DMs or segments for one launch
+    assert call(P, 65536, 5, 4, 64.0, 16.0, P, 1 << 40, P, P, P, None) == cdmt.CDMT_E_SHAPE
+    assert call(P, 1, 65536 * 1024 + 1, 4, 64.0, 16.0, P, 1 << 40, P, P, P,
+                None) == cdmt.CDMT_E_SHAPE
+    # workspace one byte short
+    assert call(P, 2, 1025, 4, 64.0, 16.0, P, 2 * 2 * 4 * 16 - 1, P, P, P,
+                None) == cdmt.CDMT_E_WORKSPACE

@@ -88,3 +88,24 @@ def test_lofar_full_size_sampled_parity(hip_lib):
     # DM tile 1: 128 DM tiles x 179712 chunks needs two launches
     out_c = run(dm_tile=1, chirp_exact=1)
     assert bool(torch.equal(out_c, out_b))
+
+    # redigitisation of the full filterbank, sampled (DM, channel) series
+    # against the oracle's statistics; the bytes follow from the parameters
+    from oracle import redigit
+    del out_c
+    codes, mean, scale = hip_lib.redigitise(out_b, 64.0, 16.0)
+    torch.cuda.synchronize()
+    worst = 0
+    for d, ch in [(0, 0), (5, 4607), (64, 1234), (127, 2048), (100, 17), (33, 3333)]:
+        series = out_b[d, :, ch].cpu().numpy()[None, :, None]
+        m_ref, k_ref = redigit.parameters(series, 16.0)
+        m, k = mean[d, ch].item(), scale[d, ch].item()
+        um = abs(int(np.float32(m).view(np.int32)) - int(m_ref[0, 0].view(np.int32)))
+        uk = abs(int(np.float32(k).view(np.int32)) - int(k_ref[0, 0].view(np.int32)))
+        worst = max(worst, um, uk)
+        got = codes[d, :, ch].cpu().numpy()
+        want = redigit.quantise(series, np.array([[m]], np.float32), np.array([[k]], np.float32),
+                                64.0)[0, :, 0]
+        assert np.array_equal(got, want), (d, ch)
+    print(f"redigitise LOFAR: sampled parameters within {worst} ulp", flush=True)
+    assert worst <= 1
