@@ -172,6 +172,72 @@ int cdmt_redigitise(const float *filterbank, int ndm, long long ntime, int nchan
                     float counts_per_sigma, void *workspace, size_t ws_bytes,
                     unsigned char *codes, float *mean, float *scale, void *hip_stream);
 
+/*
+ * Batches of beams.  The paper's survey processes several tied-array beams
+ * per source (Sec. 4), each a separate coherent-dedispersion job.  A batch
+ * runs any number of such jobs, each with its own plan (subbands, N_bin,
+ * channels, overlap, ndec, nu0 mode), input, DM list (any length) and
+ * output, as: the forward stage of every beam, then one persistent launch of
+ * the FP32 DM stage per distinct M_bin = N_bin / n_c among the beams (one
+ * launch when all share M_bin), whose workgroups take (beam, chunk group, DM
+ * tile) items from per-XCD work queues until all are done.  Results are
+ * bitwise equal to cdmt_dedisperse of each beam with the same DM tile.
+ * Restrictions: FP32 precision, 16 bins per lane, M_bin <= 4096
+ * (CDMT_E_UNSUPPORTED otherwise).
+ */
+typedef struct cdmt_batch_s *cdmt_batch_t;
+
+typedef struct {
+    cdmt_plan_t plan;          /* the beam's plan (used during create and runs)           */
+    int nblock;                /* blocks of this beam, >= 1                               */
+    const void *voltages;      /* device, as for cdmt_forward                             */
+    const double *dm_list;     /* host, ndm finite values, read during create only        */
+    int ndm;                   /* >= 1                                                    */
+    float *out;                /* device [ndm][ntime_out][nchan_out] of this beam         */
+} cdmt_beam_t;
+
+enum cdmt_batch_opt {
+    CDMT_BATCH_DM_TILE = 0,    /* DM trials per item for every beam, 1..16; 0 = each plan's */
+    CDMT_BATCH_WG_PER_CU = 1,  /* persistent workgroups per compute unit, 1..8 (default 2)  */
+    CDMT_BATCH_ITEMS = 2,      /* (get only) work items of the DM stage                      */
+    CDMT_BATCH_LAUNCHES = 3    /* (get only) persistent launches (one per distinct M_bin)    */
+};
+
+/* Workspace for a batch: every beam's spectra (cdmt_workspace_size), the DM
+ * lists, the item table and the queue counters, 256-byte aligned. */
+int cdmt_batch_workspace_size(const cdmt_beam_t *beams, int nbeam, size_t *bytes);
+
+/* Validate the beams (as cdmt_dedisperse would), copy the DM lists and the
+ * item table into the caller's workspace (synchronous host-to-device copies,
+ * the only ones this library makes) and return a batch.  The plans, device
+ * buffers and workspace must outlive the batch. */
+int cdmt_batch_create(cdmt_batch_t *out, const cdmt_beam_t *beams, int nbeam, void *workspace,
+                      size_t ws_bytes);
+
+/* Change an option (enum cdmt_batch_opt).  Rewrites the item table after a
+ * device-wide synchronisation; a captured graph is captured again on its
+ * next run. */
+int cdmt_batch_set(cdmt_batch_t batch, int opt, int value);
+int cdmt_batch_get(cdmt_batch_t batch, int opt, long long *value);
+
+/* Enqueue the whole batch on hip_stream (NULL = default stream). */
+int cdmt_batch_run(cdmt_batch_t batch, void *hip_stream);
+
+/* The same work as a HIP graph: captured from hip_stream (which must be a
+ * created stream, not NULL) on the first call or after an option changed,
+ * then replayed with one hipGraphLaunch per call.  The graph holds no memset
+ * nodes (the queue counters are cleared by a kernel). */
+int cdmt_batch_run_graph(cdmt_batch_t batch, void *hip_stream);
+
+/* Time the batch on hip_stream for every DM tile in {4, 8, 16} and 2 or 4
+ * workgroups per CU (reps runs each after one warm-up), keep the fastest
+ * setting and return its time per run in *best_ms (may be NULL).  Writes the
+ * beams' outputs. */
+int cdmt_batch_autotune(cdmt_batch_t batch, void *hip_stream, int reps, float *best_ms);
+
+/* Free a batch and its graph (NULL is accepted). */
+void cdmt_batch_destroy(cdmt_batch_t batch);
+
 /* Free a plan (NULL is accepted). */
 void cdmt_destroy(cdmt_plan_t plan);
 

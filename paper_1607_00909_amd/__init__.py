@@ -31,7 +31,18 @@ CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
 EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
            "cdmt_output_shape", "cdmt_workspace_size", "cdmt_forward",
            "cdmt_dedisperse_spectra", "cdmt_dedisperse", "cdmt_destroy", "cdmt_status_string",
-           "cdmt_redigitise_workspace_size", "cdmt_redigitise")
+           "cdmt_redigitise_workspace_size", "cdmt_redigitise",
+           "cdmt_batch_workspace_size", "cdmt_batch_create", "cdmt_batch_set", "cdmt_batch_get",
+           "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy")
+# enum cdmt_batch_opt
+CDMT_BATCH_DM_TILE, CDMT_BATCH_WG_PER_CU, CDMT_BATCH_ITEMS, CDMT_BATCH_LAUNCHES = 0, 1, 2, 3
+
+
+class Beam(ctypes.Structure):
+    """cdmt_beam_t: one beam of a batch."""
+    _fields_ = [("plan", ctypes.c_void_p), ("nblock", ctypes.c_int),
+                ("voltages", ctypes.c_void_p), ("dm_list", ctypes.POINTER(ctypes.c_double)),
+                ("ndm", ctypes.c_int), ("out", ctypes.c_void_p)]
 
 _lib = None
 _lock = threading.Lock()
@@ -76,6 +87,16 @@ def load():
         F = ctypes.c_float
         lib.cdmt_redigitise_workspace_size.argtypes = [I, LL, I, ctypes.POINTER(Z)]
         lib.cdmt_redigitise.argtypes = [P, I, LL, I, F, F, P, Z, P, P, P, P]
+        BP = ctypes.POINTER(Beam)
+        lib.cdmt_batch_workspace_size.argtypes = [BP, I, ctypes.POINTER(Z)]
+        lib.cdmt_batch_create.argtypes = [ctypes.POINTER(P), BP, I, P, Z]
+        lib.cdmt_batch_set.argtypes = [P, I, I]
+        lib.cdmt_batch_get.argtypes = [P, I, ctypes.POINTER(LL)]
+        lib.cdmt_batch_run.argtypes = [P, P]
+        lib.cdmt_batch_run_graph.argtypes = [P, P]
+        lib.cdmt_batch_autotune.argtypes = [P, P, I, ctypes.POINTER(F)]
+        lib.cdmt_batch_destroy.argtypes = [P]
+        lib.cdmt_batch_destroy.restype = None
         for name in EXPORTS:
             if not hasattr(lib, name):
                 raise RuntimeError(f"{LIB_PATH} does not export {name}")
@@ -196,6 +217,102 @@ def redigitise(fb, zero=64.0, counts_per_sigma=16.0, workspace=None, stream=None
     return codes, mean, scale
 
 
+def cdmt_batch_workspace_size(beams, nbeam) -> int:
+    v = ctypes.c_size_t()
+    _check(load().cdmt_batch_workspace_size(beams, nbeam, ctypes.byref(v)),
+           "cdmt_batch_workspace_size")
+    return v.value
+
+
+def cdmt_batch_create(beams, nbeam, workspace, ws_bytes) -> int:
+    h = ctypes.c_void_p()
+    _check(load().cdmt_batch_create(ctypes.byref(h), beams, nbeam, workspace, ws_bytes),
+           "cdmt_batch_create")
+    return h.value
+
+
+def cdmt_batch_set(batch, opt, value) -> None:
+    _check(load().cdmt_batch_set(batch, opt, value), "cdmt_batch_set")
+
+
+def cdmt_batch_get(batch, opt) -> int:
+    v = ctypes.c_longlong()
+    _check(load().cdmt_batch_get(batch, opt, ctypes.byref(v)), "cdmt_batch_get")
+    return v.value
+
+
+def cdmt_batch_run(batch, stream) -> None:
+    _check(load().cdmt_batch_run(batch, stream), "cdmt_batch_run")
+
+
+def cdmt_batch_run_graph(batch, stream) -> None:
+    _check(load().cdmt_batch_run_graph(batch, stream), "cdmt_batch_run_graph")
+
+
+def cdmt_batch_autotune(batch, stream, reps) -> float:
+    v = ctypes.c_float()
+    _check(load().cdmt_batch_autotune(batch, stream, reps, ctypes.byref(v)),
+           "cdmt_batch_autotune")
+    return v.value
+
+
+def cdmt_batch_destroy(batch) -> None:
+    if batch:
+        load().cdmt_batch_destroy(batch)
+
+
+class Batch:
+    """Several beams (Plan, nblock, device voltages, DM list, device output)
+    run as one batch; torch supplies the workspace and the streams."""
+
+    def __init__(self, beams, device="cuda"):
+        import torch
+        load()
+        self._keep = []
+        arr = (Beam * len(beams))()
+        for i, (plan, nblock, x, dms, out) in enumerate(beams):
+            plan._check_voltages(x, nblock)
+            _, ntout, nch = plan.shape(nblock)
+            if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
+                    or tuple(out.shape) != (len(dms), ntout, nch)):
+                raise ValueError(f"beam {i}: output must be a contiguous float32 "
+                                 f"{(len(dms), ntout, nch)} device tensor")
+            d, n = _dm_array(dms)
+            arr[i] = Beam(plan.handle, nblock, x.data_ptr(), d, n, out.data_ptr())
+            self._keep += [plan, x, out, d]
+        n = cdmt_batch_workspace_size(arr, len(beams))
+        self.workspace = torch.empty(max(1, n), dtype=torch.uint8, device=device)
+        self.handle = cdmt_batch_create(arr, len(beams), ctypes.c_void_p(self.workspace.data_ptr()),
+                                        self.workspace.numel())
+
+    def __del__(self):
+        try:
+            cdmt_batch_destroy(self.handle)
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def set(self, opt, value):
+        cdmt_batch_set(self.handle, opt, value)
+
+    def get(self, opt):
+        return cdmt_batch_get(self.handle, opt)
+
+    def run(self, stream=None):
+        cdmt_batch_run(self.handle, self._stream(stream))
+
+    def run_graph(self, stream):
+        cdmt_batch_run_graph(self.handle, self._stream(stream))
+
+    def autotune(self, stream=None, reps=2):
+        return cdmt_batch_autotune(self.handle, self._stream(stream), reps)
+
+
 # ------------------------------------------------- torch-facing wrapper ----
 
 class Plan:
@@ -279,4 +396,5 @@ def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
 
 
 __all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
-                                                          "dm_seconds", "redigitise", "EXPORTS"]
+                                                          "dm_seconds", "redigitise", "Batch",
+                                                          "Beam", "EXPORTS"]

@@ -258,20 +258,25 @@ struct FusedShape {
     static constexpr int MIN_WAVES = R == 8 ? 4 : 1;
 };
 
-template <int M, int R, bool RECUR>
-__global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVES)) void fused_dedisperse(FusedArgs a,
-                                                                         DmList dl) {
+// DM values of a launch: passed by value in the kernel arguments, or read
+// from device memory (batched launches); the index is uniform over the
+// workgroup, so either way the load is scalar
+struct ArgDms {
+    const DmList &dl;
+    __device__ __forceinline__ double operator[](int i) const { return dl.dm[i]; }
+};
+struct MemDms {
+    const double *p;
+    __device__ __forceinline__ double operator[](int i) const { return p[i]; }
+};
+
+// One work item: chunk group cg (C channel chunks) and DM tile dt.
+template <int M, int R, bool RECUR, class DMS>
+__device__ __forceinline__ void dm_item(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
     using Sh = FusedShape<M, R>;
     constexpr int T = Sh::T;
     constexpr int C = Sh::C;
     constexpr int STRIDE = Sh::STRIDE;
-    __shared__ cpair sh[C * STRIDE];
-
-    const int lw = xcd_remap(blockIdx.x, gridDim.x);
-    const int ci = lw % a.inner;
-    const int rest = lw / a.inner;
-    const int dt = rest % a.ndt;
-    const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
 
     const int t = threadIdx.x;
     const int f = t / T, tt = t % T;
@@ -321,7 +326,7 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
         // P(d0) = raw exp(i pi dm(d0) g2) and the per-DM step, in double
 #pragma unroll
         for (int q = 0; q < R; ++q) {
-            raw[q] = cdmt::pmul(raw[q], cis_pi_f64(dl.dm[d0] * g2[q]));
+            raw[q] = cdmt::pmul(raw[q], cis_pi_f64(dms[d0] * g2[q]));
             step[q] = cis_pi_f64(a.dm_step * g2[q]);
         }
     }
@@ -336,7 +341,7 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
                 raw[q] = cdmt::pmul(raw[q], step[q]);
             }
         } else {
-            const double dm = dl.dm[d];
+            const double dm = dms[d];
 #pragma unroll
             for (int q = 0; q < R; ++q) {
                 // phase in half-cycles, reduced in FP64 to n + r with |r| <= 1/2
@@ -386,6 +391,19 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
         }
         __syncthreads();
     }
+}
+
+template <int M, int R, bool RECUR>
+__global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVES)) void fused_dedisperse(FusedArgs a,
+                                                                         DmList dl) {
+    using Sh = FusedShape<M, R>;
+    __shared__ cpair sh[Sh::C * Sh::STRIDE];
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int ci = lw % a.inner;
+    const int rest = lw / a.inner;
+    const int dt = rest % a.ndt;
+    const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
+    dm_item<M, R, RECUR>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -828,6 +846,68 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
 }
 
 // ---------------------------------------------------------------------------
+// Batches: several beams, each with its own plan (subbands, N_bin, channels,
+// overlap), input, DM list and output, through the FP32 DM stage in one
+// persistent launch per M_bin present and per form of the transfer function
+// (recurrence for arithmetic DM lists, else exact): one launch when every
+// beam has the same M_bin and arithmetic DM lists.  Work items are (beam, chunk group, DM tile); items are
+// numbered beam by beam, and within a beam with the DM tiles of a chunk
+// group consecutive (so they share the chunk in L2).  The item range is split
+// into one contiguous queue per XCD; workgroup w serves queue w % 8 (the
+// dispatcher places workgroups on XCDs round-robin) and takes items from it
+// with an atomic counter until the queue is exhausted, so every workgroup
+// exits once its queue is drained.
+
+struct BatchBeam {
+    FusedArgs a;            // the beam's DM-stage arguments (cg0 = 0)
+    long long item0;        // first work item of the beam within its launch
+    const double *dms;      // the beam's DM list in device memory
+};
+
+constexpr int kBatchQueues = 8;
+
+__global__ void batch_reset(unsigned long long *ctr, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        ctr[i] = 0;
+}
+
+template <int M, bool RECUR>
+__global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__ beams, int nbeam,
+                                                   long long total,
+                                                   unsigned long long *__restrict__ ctr) {
+    using Sh = FusedShape<M, 16>;
+    static_assert(Sh::WG == 256, "batched launches use 256-lane workgroups");
+    __shared__ cpair sh[Sh::C * Sh::STRIDE];
+    __shared__ long long s_item;
+    const int q = blockIdx.x % kBatchQueues;
+    const long long lo = total * q / kBatchQueues;
+    const long long hi = total * (q + 1) / kBatchQueues;
+    for (;;) {
+        if (threadIdx.x == 0)
+            s_item = lo + (long long)atomicAdd(&ctr[q], 1ULL);
+        __syncthreads();
+        // the same value in every lane: keep it (and all that follows from it) scalar
+        const unsigned long long raw_item = (unsigned long long)s_item;
+        const long long item = (long long)(
+            ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(raw_item >> 32)) << 32) |
+            (unsigned)__builtin_amdgcn_readfirstlane((unsigned)raw_item));
+        __syncthreads();
+        if (item >= hi)
+            break;
+        int b = 0;
+        while (b + 1 < nbeam && beams[b + 1].item0 <= item)
+            ++b;
+        const FusedArgs &a = beams[b].a;
+        const long long local = item - beams[b].item0;
+        const int ci = (int)(local % a.inner);
+        const long long rest = local / a.inner;
+        const int dt = (int)(rest % a.ndt);
+        const int cg = (int)((rest / a.ndt) * a.inner + ci);
+        dm_item<M, 16, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side.
 
 std::mutex g_init_mu;
@@ -1017,8 +1097,7 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
     return CDMT_OK;
 }
 
-int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *dms, int ndm,
-                      float *out, hipStream_t st) {
+FusedArgs fused_args(const cdmt_plan_s *p, void *ws, int nblock, float *out) {
     FusedArgs a;
     std::memset(&a, 0, sizeof(a));
     a.spec = reinterpret_cast<const cpair *>(ws);
@@ -1042,6 +1121,12 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
     // recurrence allowed when every DM sits on the progression to within a
     // phase error of 1e-7 half-cycles (dm_step carries the tolerance here)
     a.dm_step = p->chirp_exact ? 0.0 : 1e-7 / max_half_cycles_per_dm(p);
+    return a;
+}
+
+int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *dms, int ndm,
+                      float *out, hipStream_t st) {
+    const FusedArgs a = fused_args(p, ws, nblock, out);
     const bool r8 = p->lane_bins == 8;
     switch (p->m) {
     case 64: return launch_fused_m<64, 16>(a, dms, ndm, st);
@@ -1297,6 +1382,364 @@ const char *cdmt_status_string(int status) {
     case CDMT_E_UNSUPPORTED: return "configuration not supported by this build";
     default: return "unknown status";
     }
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batches of beams (host side).
+
+struct cdmt_batch_s {
+    std::vector<cdmt_beam_t> beams;           // the caller's descriptors
+    std::vector<std::vector<double>> dms;     // host copies of the DM lists
+    std::vector<size_t> spec_off;             // per beam: spectra in the workspace
+    size_t dm_off = 0, tab_off = 0, ctr_off = 0;
+    char *ws = nullptr;
+    int device = 0;
+    int dm_tile = 0;                          // 0: each plan's own
+    int wg_per_cu = 2;
+    long long total = 0;                      // work items over all launches
+    struct Launch {
+        int m, recur, first, count;           // M_bin, form, table rows [first, first + count)
+        long long items;
+    };
+    std::vector<Launch> launches;             // one persistent launch per (M_bin, form)
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t graph_stream = nullptr;
+    bool dirty = true;                        // the graph must be captured again
+};
+
+namespace {
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int batch_layout(const cdmt_beam_t *beams, int nbeam, std::vector<size_t> *spec_off,
+                 size_t *dm_off, size_t *tab_off, size_t *ctr_off, size_t *total) {
+    if (!beams || nbeam < 1 || nbeam > 4096)
+        return CDMT_E_ARG;
+    size_t off = 0;
+    size_t ndm_all = 0;
+    for (int b = 0; b < nbeam; ++b) {
+        const cdmt_beam_t &B = beams[b];
+        const cdmt_plan_s *p = B.plan;
+        if (!p || B.nblock < 1 || B.ndm < 1 || !B.voltages || !B.dm_list || !B.out)
+            return CDMT_E_ARG;
+        if (p->precision != 0 || p->lane_bins != 16)
+            return CDMT_E_UNSUPPORTED;          // FP32, 16 bins per lane
+        if (p->m > 4096)
+            return CDMT_E_UNSUPPORTED;          // 512-lane workgroups: use cdmt_dedisperse
+        if ((long long)B.nblock * p->nsub * p->nchan > 0x7fffffffLL)
+            return CDMT_E_SHAPE;
+        const double bound = max_half_cycles_per_dm(p);
+        for (int i = 0; i < B.ndm; ++i)
+            if (!std::isfinite(B.dm_list[i]) || std::fabs(B.dm_list[i]) * bound >= 1073741824.0)
+                return CDMT_E_ARG;
+        size_t w = 0;
+        workspace_bytes(p, B.nblock, &w);
+        if (spec_off)
+            spec_off->push_back(off);
+        off = align256(off + w);
+        ndm_all += (size_t)B.ndm;
+    }
+    *dm_off = off;
+    off = align256(off + ndm_all * sizeof(double));
+    *tab_off = off;
+    off = align256(off + (size_t)nbeam * sizeof(BatchBeam));
+    *ctr_off = off;
+    *total = off + 14 * kBatchQueues * sizeof(unsigned long long);  // 7 M_bin x 2 forms
+    return CDMT_OK;
+}
+
+// device table of the batch for its current settings (synchronous copy):
+// rows grouped by M_bin, one persistent launch per group
+int batch_upload(cdmt_batch_s *bt) {
+    const int nbeam = (int)bt->beams.size();
+    std::vector<BatchBeam> tab;
+    std::vector<double> dmall;
+    std::vector<size_t> dm_at(nbeam);
+    for (int b = 0; b < nbeam; ++b) {
+        dm_at[b] = dmall.size();
+        dmall.insert(dmall.end(), bt->dms[b].begin(), bt->dms[b].end());
+    }
+    bt->launches.clear();
+    bt->total = 0;
+    std::vector<BatchBeam> rows(nbeam);
+    std::vector<int> rec(nbeam);
+    for (int b = 0; b < nbeam; ++b) {
+        const cdmt_beam_t &B = bt->beams[b];
+        const cdmt_plan_s *p = B.plan;
+        BatchBeam &T = rows[b];
+        std::memset(&T, 0, sizeof(T));
+        T.a = fused_args(p, bt->ws + bt->spec_off[b], B.nblock, B.out);
+        T.a.dm_tile = bt->dm_tile > 0 ? bt->dm_tile : p->dm_tile;
+        const int C = 4096 / p->m;              // chunks per 256-lane workgroup
+        T.a.inner = p->nchan >= C ? p->nchan / C : 1;
+        T.a.ndm = B.ndm;
+        T.a.ndt = (B.ndm + T.a.dm_tile - 1) / T.a.dm_tile;
+        const std::vector<double> &d = bt->dms[b];
+        const bool recur = T.a.dm_step != 0.0 && T.a.dm_tile > 1 && B.ndm > 1 &&
+                           arithmetic(d.data(), B.ndm, T.a.dm_step);
+        T.a.dm_step = recur ? d[1] - d[0] : 0.0;
+        rec[b] = recur ? 1 : 0;
+        T.dms = reinterpret_cast<const double *>(bt->ws + bt->dm_off) + dm_at[b];
+    }
+    for (int m = 64; m <= 4096; m *= 2) {
+        for (int r = 1; r >= 0; --r) {
+            cdmt_batch_s::Launch L{m, r, (int)tab.size(), 0, 0};
+            for (int b = 0; b < nbeam; ++b) {
+                if (bt->beams[b].plan->m != m || rec[b] != r)
+                    continue;
+                BatchBeam T = rows[b];
+                const int C = 4096 / m;
+                T.item0 = L.items;
+                L.items += ((long long)T.a.nchunks + C - 1) / C * T.a.ndt;
+                tab.push_back(T);
+                ++L.count;
+            }
+            if (L.count) {
+                bt->launches.push_back(L);
+                bt->total += L.items;
+            }
+        }
+    }
+    if (hipMemcpy(bt->ws + bt->dm_off, dmall.data(), dmall.size() * sizeof(double),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return CDMT_E_DEVICE;
+    if (hipMemcpy(bt->ws + bt->tab_off, tab.data(), tab.size() * sizeof(BatchBeam),
+                  hipMemcpyHostToDevice) != hipSuccess)
+        return CDMT_E_DEVICE;
+    bt->dirty = true;
+    return CDMT_OK;
+}
+
+template <int M>
+void batch_launch(int recur, const BatchBeam *tab, int count, long long items,
+                  unsigned long long *ctr, int grid, hipStream_t st) {
+    if (recur)
+        dm_batch<M, true><<<grid, 256, 0, st>>>(tab, count, items, ctr);
+    else
+        dm_batch<M, false><<<grid, 256, 0, st>>>(tab, count, items, ctr);
+}
+
+int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
+    for (size_t b = 0; b < bt->beams.size(); ++b) {
+        const cdmt_beam_t &B = bt->beams[b];
+        const int r = launch_forward(B.plan, bt->ws + bt->spec_off[b], B.voltages, B.nblock, st);
+        if (r)
+            return r;
+    }
+    unsigned long long *ctr = reinterpret_cast<unsigned long long *>(bt->ws + bt->ctr_off);
+    batch_reset<<<1, 128, 0, st>>>(ctr, 14 * kBatchQueues);
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, bt->device) !=
+        hipSuccess || ncu < 1)
+        return CDMT_E_DEVICE;
+    const int grid = ncu * bt->wg_per_cu;
+    const BatchBeam *tab = reinterpret_cast<const BatchBeam *>(bt->ws + bt->tab_off);
+    for (size_t k = 0; k < bt->launches.size(); ++k) {
+        const cdmt_batch_s::Launch &L = bt->launches[k];
+        unsigned long long *c = ctr + k * kBatchQueues;
+        const BatchBeam *t = tab + L.first;
+        switch (L.m) {
+        case 64: batch_launch<64>(L.recur, t, L.count, L.items, c, grid, st); break;
+        case 128: batch_launch<128>(L.recur, t, L.count, L.items, c, grid, st); break;
+        case 256: batch_launch<256>(L.recur, t, L.count, L.items, c, grid, st); break;
+        case 512: batch_launch<512>(L.recur, t, L.count, L.items, c, grid, st); break;
+        case 1024: batch_launch<1024>(L.recur, t, L.count, L.items, c, grid, st); break;
+        case 2048: batch_launch<2048>(L.recur, t, L.count, L.items, c, grid, st); break;
+        case 4096: batch_launch<4096>(L.recur, t, L.count, L.items, c, grid, st); break;
+        default: return CDMT_E_UNSUPPORTED;
+        }
+        if (hipGetLastError() != hipSuccess)
+            return CDMT_E_DEVICE;
+    }
+    return CDMT_OK;
+}
+
+void batch_drop_graph(cdmt_batch_s *bt) {
+    if (bt->exec)
+        (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph)
+        (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    bt->graph_stream = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdmt_batch_workspace_size(const cdmt_beam_t *beams, int nbeam, size_t *bytes) {
+    if (!bytes)
+        return CDMT_E_ARG;
+    size_t a, b, c;
+    return batch_layout(beams, nbeam, nullptr, &a, &b, &c, bytes);
+}
+
+int cdmt_batch_create(cdmt_batch_t *out, const cdmt_beam_t *beams, int nbeam, void *workspace,
+                      size_t ws_bytes) {
+    if (!out)
+        return CDMT_E_ARG;
+    *out = nullptr;
+    std::vector<size_t> off;
+    size_t dm_off, tab_off, ctr_off, need;
+    int st = batch_layout(beams, nbeam, &off, &dm_off, &tab_off, &ctr_off, &need);
+    if (st)
+        return st;
+    if (!workspace)
+        return CDMT_E_ARG;
+    if (ws_bytes < need)
+        return CDMT_E_WORKSPACE;
+    if ((st = ensure_twiddles()))
+        return st;
+    cdmt_batch_s *bt = new cdmt_batch_s;
+    bt->beams.assign(beams, beams + nbeam);
+    for (int b = 0; b < nbeam; ++b) {
+        bt->dms.emplace_back(beams[b].dm_list, beams[b].dm_list + beams[b].ndm);
+        bt->beams[b].dm_list = nullptr;       // read during this call only
+    }
+    bt->spec_off = off;
+    bt->dm_off = dm_off;
+    bt->tab_off = tab_off;
+    bt->ctr_off = ctr_off;
+    bt->ws = static_cast<char *>(workspace);
+    if (hipGetDevice(&bt->device) != hipSuccess || (st = batch_upload(bt))) {
+        delete bt;
+        return st ? st : CDMT_E_DEVICE;
+    }
+    *out = bt;
+    return CDMT_OK;
+}
+
+int cdmt_batch_set(cdmt_batch_t bt, int opt, int value) {
+    if (!bt)
+        return CDMT_E_ARG;
+    switch (opt) {
+    case CDMT_BATCH_DM_TILE:
+        if (value < 0 || value > 16)
+            return CDMT_E_ARG;
+        // the table is rewritten in place: no run of the batch may be in flight
+        if (hipDeviceSynchronize() != hipSuccess)
+            return CDMT_E_DEVICE;
+        bt->dm_tile = value;
+        return batch_upload(bt);
+    case CDMT_BATCH_WG_PER_CU:
+        if (value < 1 || value > 8)
+            return CDMT_E_ARG;
+        bt->wg_per_cu = value;
+        bt->dirty = true;
+        return CDMT_OK;
+    default: return CDMT_E_ARG;
+    }
+}
+
+int cdmt_batch_get(cdmt_batch_t bt, int opt, long long *value) {
+    if (!bt || !value)
+        return CDMT_E_ARG;
+    switch (opt) {
+    case CDMT_BATCH_DM_TILE: *value = bt->dm_tile; return CDMT_OK;
+    case CDMT_BATCH_WG_PER_CU: *value = bt->wg_per_cu; return CDMT_OK;
+    case CDMT_BATCH_ITEMS: *value = bt->total; return CDMT_OK;
+    case CDMT_BATCH_LAUNCHES: *value = (long long)bt->launches.size(); return CDMT_OK;
+    default: return CDMT_E_ARG;
+    }
+}
+
+int cdmt_batch_run(cdmt_batch_t bt, void *hip_stream) {
+    if (!bt)
+        return CDMT_E_ARG;
+    return batch_enqueue(bt, static_cast<hipStream_t>(hip_stream));
+}
+
+int cdmt_batch_run_graph(cdmt_batch_t bt, void *hip_stream) {
+    if (!bt || !hip_stream)
+        return CDMT_E_ARG;                     // capture needs a created stream
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (bt->dirty || !bt->exec || bt->graph_stream != st) {
+        batch_drop_graph(bt);
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return CDMT_E_DEVICE;
+        const int r = batch_enqueue(bt, st);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (r || e != hipSuccess || !g) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return r ? r : CDMT_E_DEVICE;
+        }
+        bt->graph = g;
+        if (hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+            batch_drop_graph(bt);
+            return CDMT_E_DEVICE;
+        }
+        bt->graph_stream = st;
+        bt->dirty = false;
+    }
+    return hipGraphLaunch(bt->exec, st) == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
+}
+
+int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best_ms) {
+    if (!bt || reps < 1)
+        return CDMT_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess)
+        return CDMT_E_DEVICE;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return CDMT_E_DEVICE;
+    }
+    static const int kTiles[] = {4, 8, 16};
+    static const int kWg[] = {2, 4};
+    float best = 0.f;
+    int bt_tile = 16, bt_wg = 2, r = CDMT_OK;
+    for (int tile : kTiles) {
+        for (int wg : kWg) {
+            if ((r = cdmt_batch_set(bt, CDMT_BATCH_DM_TILE, tile)) ||
+                (r = cdmt_batch_set(bt, CDMT_BATCH_WG_PER_CU, wg)))
+                break;
+            if ((r = batch_enqueue(bt, st)))                  // warm-up
+                break;
+            float ms = 0.f;
+            if (hipEventRecord(e0, st) != hipSuccess) { r = CDMT_E_DEVICE; break; }
+            for (int i = 0; i < reps && !r; ++i)
+                r = batch_enqueue(bt, st);
+            if (r)
+                break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                r = CDMT_E_DEVICE;
+                break;
+            }
+            ms /= reps;
+            if (best == 0.f || ms < best) {
+                best = ms;
+                bt_tile = tile;
+                bt_wg = wg;
+            }
+        }
+        if (r)
+            break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r)
+        return r;
+    if ((r = cdmt_batch_set(bt, CDMT_BATCH_DM_TILE, bt_tile)) ||
+        (r = cdmt_batch_set(bt, CDMT_BATCH_WG_PER_CU, bt_wg)))
+        return r;
+    if (best_ms)
+        *best_ms = best;
+    return CDMT_OK;
+}
+
+void cdmt_batch_destroy(cdmt_batch_t bt) {
+    if (!bt)
+        return;
+    batch_drop_graph(bt);
+    delete bt;
 }
 
 }  // extern "C"

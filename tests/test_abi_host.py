@@ -195,3 +195,58 @@ def test_redigitise_validation(lib):
     # workspace one byte short
     assert call(P, 2, 1025, 4, 64.0, 16.0, P, 2 * 2 * 4 * 16 - 1, P, P, P,
                 None) == cdmt.CDMT_E_WORKSPACE
+
+
+def test_batch_validation(lib):
+    """cdmt_batch_* argument checks, all returned before any device work."""
+    import ctypes
+    p1 = cdmt.cdmt_plan(*GOOD)                                   # M = 2048
+    p2 = cdmt.cdmt_plan(2, 120.0, 0.1953125, 65536, 4096, 8, 4)  # M = 8192
+    p3 = cdmt.cdmt_plan(2, 120.0, 0.1953125, 65536, 4096, 16, 4)
+    try:
+        dms = (ctypes.c_double * 3)(0.0, 1.0, 2.0)
+        P = ctypes.c_void_p(256)
+
+        def beams(*specs):
+            arr = (cdmt.Beam * len(specs))()
+            for i, (plan, nblock, ndm, d) in enumerate(specs):
+                arr[i] = cdmt.Beam(plan, nblock, P.value, d, ndm, P.value)
+            return arr
+
+        z = ctypes.c_size_t()
+        good = beams((p1, 2, 3, dms), (p3, 1, 3, dms))
+        assert lib.cdmt_batch_workspace_size(good, 2, ctypes.byref(z)) == cdmt.CDMT_OK
+        w1 = cdmt.cdmt_workspace_size(p1, 2)
+        w3 = cdmt.cdmt_workspace_size(p3, 1)
+        up = lambda v: (v + 255) // 256 * 256
+        # spectra of each beam, the DM lists, the table, 14 x 8 queue counters
+        assert z.value > up(up(w1) + w3) + 6 * 8
+        assert z.value < up(up(w1) + w3) + 4096 + 14 * 8 * 8
+        h = ctypes.c_void_p()
+        assert lib.cdmt_batch_create(ctypes.byref(h), good, 0, P, 1 << 40) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_create(ctypes.byref(h), good, 2, None, 1 << 40) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_create(ctypes.byref(h), good, 2, P, z.value - 1) == \
+            cdmt.CDMT_E_WORKSPACE
+        assert lib.cdmt_batch_create(ctypes.byref(h), beams((p2, 1, 3, dms)), 1, P,
+                                     1 << 40) == cdmt.CDMT_E_UNSUPPORTED      # M = 8192
+        cdmt.cdmt_plan_set(p3, cdmt.CDMT_OPT_PRECISION, 2)
+        assert lib.cdmt_batch_create(ctypes.byref(h), beams((p3, 1, 3, dms)), 1, P,
+                                     1 << 40) == cdmt.CDMT_E_UNSUPPORTED      # FP32 only
+        cdmt.cdmt_plan_set(p3, cdmt.CDMT_OPT_PRECISION, 0)
+        assert lib.cdmt_batch_create(ctypes.byref(h), beams((p1, 0, 3, dms)), 1, P,
+                                     1 << 40) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_create(ctypes.byref(h), beams((p1, 1, 0, dms)), 1, P,
+                                     1 << 40) == cdmt.CDMT_E_ARG
+        bad = (ctypes.c_double * 3)(0.0, float("nan"), 2.0)
+        assert lib.cdmt_batch_create(ctypes.byref(h), beams((p1, 1, 3, bad)), 1, P,
+                                     1 << 40) == cdmt.CDMT_E_ARG
+        assert h.value is None
+        v = ctypes.c_longlong()
+        assert lib.cdmt_batch_set(None, 0, 4) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_get(None, 0, ctypes.byref(v)) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_run(None, None) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_run_graph(None, P) == cdmt.CDMT_E_ARG
+        lib.cdmt_batch_destroy(None)
+    finally:
+        for p in (p1, p2, p3):
+            cdmt.cdmt_destroy(p)

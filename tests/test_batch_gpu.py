@@ -1,0 +1,150 @@
+"""Batches of beams (several plans, inputs, DM lists and outputs in one
+persistent launch per M_bin) through the C ABI.
+
+The batched DM stage runs the same per-item arithmetic as the single-beam
+kernel, so each beam's output must be bitwise equal to cdmt_dedisperse of that
+beam with the same DM tile.  Each beam is also checked against the FP64
+oracle on one (subband, block) pair, and the graph form must reproduce the
+eager run on every replay, with other work in between."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_00909_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@dataclasses.dataclass
+class BeamSpec:
+    nsub: int
+    f_centre: float
+    nfft: int
+    noverlap: int
+    nchan: int
+    ndec: int
+    nblock: int
+    dms: list
+    kind: str
+    chirp_ref: int = oracle.CHANNEL
+
+
+# uneven subband counts, N_bin, channel counts (M_bin 4096, 4096, 2048, 1024,
+# 512), DM counts (ragged tiles, more than 256) and DM ranges; one non-arithmetic
+# DM list (exact transfer function, its own launch); both nu0 modes
+SPECS = [
+    BeamSpec(3, 150.0, 65536, 8192, 16, 8, 2, list(np.arange(0.0, 40.0, 0.5)), "ci8"),
+    BeamSpec(2, 120.0, 16384, 4096, 4, 4, 3, list(np.arange(0.0, 7.0, 1.0)), "cf32",
+             oracle.SUBBAND),
+    BeamSpec(4, 135.0, 32768, 4096, 16, 4, 2, list(np.arange(10.0, 10.0 + 0.25 * 300, 0.25)),
+             "ci8"),
+    BeamSpec(1, 170.0, 16384, 2048, 16, 2, 2, [0.0, 3.0, 4.5, 11.0, 30.0], "ci8"),
+    BeamSpec(2, 110.0, 131072, 16384, 256, 4, 1, list(np.arange(0.0, 200.0, 12.5)), "cf32"),
+]
+
+
+def _inputs(spec, seed):
+    cfg = oracle.Config(spec.nsub, spec.f_centre, synth.SUBBAND_MHZ, spec.nfft, spec.noverlap,
+                        spec.nchan, spec.ndec, chirp_ref=spec.chirp_ref)
+    x = synth.gaussian_voltages(spec.nsub, cfg.ntime_in(spec.nblock), 16.0 if spec.kind == "ci8"
+                                else 1.0, seed)
+    v = synth.encode_ci8(x)[0] if spec.kind == "ci8" else synth.encode_cf32(x)
+    return cfg, v
+
+
+def _plan(hip_lib, spec, dm_tile=None):
+    return hip_lib.Plan(spec.nsub, spec.f_centre, synth.SUBBAND_MHZ, spec.nfft, spec.noverlap,
+                        spec.nchan, spec.ndec,
+                        input_kind=hip_lib.INPUT_CI8 if spec.kind == "ci8" else hip_lib.INPUT_CF32,
+                        chirp_ref=spec.chirp_ref, dm_tile=dm_tile)
+
+
+def _setup(hip_lib, torch, specs):
+    beams, host = [], []
+    for i, sp in enumerate(specs):
+        cfg, v = _inputs(sp, 300 + i)
+        plan = _plan(hip_lib, sp)
+        _, ntout, nch = plan.shape(sp.nblock)
+        x = torch.from_numpy(v).cuda()
+        out = torch.full((len(sp.dms), ntout, nch), float("nan"), device="cuda")
+        beams.append((plan, sp.nblock, x, sp.dms, out))
+        host.append((cfg, v))
+    return beams, host
+
+
+def _single(hip_lib, sp, x, dm_tile):
+    plan = _plan(hip_lib, sp, dm_tile)
+    return plan.dedisperse(x, sp.nblock, sp.dms)
+
+
+def test_batch_matches_single_beams_and_oracle(hip_lib):
+    torch = _torch()
+    print("[gpu-case] batch of 5 beams, eager", flush=True)
+    beams, host = _setup(hip_lib, torch, SPECS)
+    batch = hip_lib.Batch(beams)
+    # M 4096 (two beams), 2048, 512 with the recurrence; M 1024 exact
+    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == 4
+    batch.run()
+    torch.cuda.synchronize()
+    for i, (sp, (plan, nblock, x, dms, out)) in enumerate(zip(SPECS, beams)):
+        assert bool(torch.isfinite(out).all()), f"beam {i}: output not fully written"
+        ref = _single(hip_lib, sp, x, 16)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"beam {i} differs from its single-beam run"
+        _, v = host[i]
+        s, b = sp.nsub - 1, sp.nblock - 1
+        cfg1 = oracle.Config(1, sp.f_centre + (s - (sp.nsub - 1) / 2) * synth.SUBBAND_MHZ,
+                             synth.SUBBAND_MHZ, sp.nfft, sp.noverlap, sp.nchan, sp.ndec,
+                             chirp_ref=sp.chirp_ref)
+        want = oracle.subband_block(cfg1, v[s:s + 1], 0, b, sp.dms)
+        cols = [(sp.nsub - 1 - s) * sp.nchan + (sp.nchan - 1 - c) for c in range(sp.nchan)]
+        tb = plan.shape(1)[1]
+        got = out[:, b * tb:(b + 1) * tb, cols].double().cpu().numpy()
+        d = got - want
+        e = float(np.sqrt((d ** 2).sum((1, 2)) / (want ** 2).sum((1, 2))).max())
+        print(f"beam {i}: M {sp.nfft // sp.nchan}, {len(sp.dms)} DMs, vs oracle {e:.2e}",
+              flush=True)
+        assert e <= 1e-5
+
+
+def test_batch_graph_replays_and_autotune(hip_lib):
+    torch = _torch()
+    print("[gpu-case] batch graph + autotune", flush=True)
+    specs = SPECS[:3]
+    beams, _ = _setup(hip_lib, torch, specs)
+    batch = hip_lib.Batch(beams)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch.run(stream)
+    stream.synchronize()
+    eager = [b[4].clone() for b in beams]
+    for rep in range(3):
+        for b in beams:
+            b[4].fill_(-1.0)                      # eager work between replays
+        torch.cuda.synchronize()
+        batch.run_graph(stream)
+        stream.synchronize()
+        for i, b in enumerate(beams):
+            assert torch.equal(b[4], eager[i]), f"replay {rep}, beam {i}"
+    best = batch.autotune(stream, reps=1)
+    stream.synchronize()
+    tile = batch.get(hip_lib.CDMT_BATCH_DM_TILE)
+    wg = batch.get(hip_lib.CDMT_BATCH_WG_PER_CU)
+    print(f"autotune: dm tile {tile}, {wg} workgroups per CU, {best:.3f} ms", flush=True)
+    assert best > 0 and tile in (4, 8, 16) and wg in (2, 4)
+    # after tuning (graph captured again) each beam equals its single run at that tile
+    batch.run_graph(stream)
+    stream.synchronize()
+    for i, (sp, b) in enumerate(zip(specs, beams)):
+        ref = _single(hip_lib, sp, b[2], tile)
+        torch.cuda.synchronize()
+        assert torch.equal(b[4], ref), f"beam {i} after autotune"
