@@ -125,6 +125,53 @@ def cpu_baseline(w, x_dev, npairs: int, threads: int, outputs=None):
                       f"extrapolated linearly"}, errors
 
 
+def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
+    """The batched workload: 24 beams, each with its own subbands, N_bin,
+    channels, overlap, DM list and output, in one persistent DM-stage launch
+    per M_bin (all beams here have M_bin = 4096: one launch), replayed as a
+    hipGraph after the autotuner picked the DM tile and the grid."""
+    import math
+    draws = synth.batch_draws()
+    beams, dm_seconds = [], 0.0
+    for i, d in enumerate(draws):
+        nov = cdmt.cdmt_noverlap_for(d.f_lo, synth.SUBBAND_MHZ, d.dm_max, d.nchan, d.ndec,
+                                     cdmt.CHIRP_CHANNEL)
+        nblock = math.ceil(synth.SUBBAND_MHZ * 1e6 / (d.nfft - nov))
+        plan = cdmt.Plan(d.nsub, d.f_centre, synth.SUBBAND_MHZ, d.nfft, nov, d.nchan, d.ndec,
+                         input_kind=cdmt.INPUT_CI8)
+        ntin, ntout, nch = plan.shape(nblock)
+        x = synth.device_noise("ci8", d.nsub, ntin, 16.0, 1607 + i, dev)
+        out = torch.empty((d.ndm, ntout, nch), dtype=torch.float32, device=dev)
+        beams.append((plan, nblock, x, list(d.dms), out))
+        dm_seconds += d.ndm * cdmt.dm_seconds(nblock, d.nfft, nov, synth.SUBBAND_MHZ)
+    batch = cdmt.Batch(beams, dev)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    tuned_ms = batch.autotune(stream, reps=reps)
+    tune_s = time.perf_counter() - t0
+    batch.run_graph(stream)                      # capture and one replay
+    stream.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        batch.run_graph(stream)
+    ev[1].record(stream)
+    stream.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    res = {"workload": f"batch-{len(draws)}beam", "beams": len(draws),
+           "value": round(dm_seconds / (ms / 1e3), 2), "unit": "DM-s/s",
+           "ms_per_run": round(ms, 3), "dm_seconds_per_run": round(dm_seconds, 3),
+           "launches": batch.get(cdmt.CDMT_BATCH_LAUNCHES),
+           "items": batch.get(cdmt.CDMT_BATCH_ITEMS),
+           "dm_tile": batch.get(cdmt.CDMT_BATCH_DM_TILE),
+           "wg_per_cu": batch.get(cdmt.CDMT_BATCH_WG_PER_CU),
+           "autotune_best_ms": round(tuned_ms, 3), "autotune_s": round(tune_s, 1),
+           "graph": True}
+    log(f"batch: {len(draws)} beams, {ms:.3f} ms per run, {res['value']} DM-s/s")
+    del batch, beams
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +187,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the other DM-stage arithmetics (mixed vs FP32 plain)")
+    ap.add_argument("--batch", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the 24-beam batched workload (persistent launch, hipGraph)")
     ap.add_argument("--redigitise", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 8-bit redigitisation of the filterbank")
     ap.add_argument("--calib-copy", action="store_true",
@@ -258,6 +307,7 @@ def main():
         "realtime_factor": round(w.data_seconds / (elapsed / args.steps), 2),
     }
     outputs = {args.precision: out}
+    o2 = None
     if args.variants and w.m == 4096:
         # the same job with the other backward-FFT arithmetics, same input
         variants = {}
@@ -327,6 +377,12 @@ def main():
         log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads")
         line["cpu_baseline"], errs = cpu_baseline(w, x, args.cpu_pairs, threads, outputs)
         line["errors_vs_oracle"] = errs
+    if args.batch:
+        # free the single-job buffers first: the batch holds ~125 GB of its own
+        del outputs, out, ws, x, o2
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        line["batch"] = batch_leg(cdmt, synth, torch, dev, args.steps, 1)
     print(json.dumps(line), flush=True)
 
 

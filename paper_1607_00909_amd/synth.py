@@ -87,6 +87,46 @@ LOFAR = Workload("lofar-hba-288sub-128dm", nsub=288, f_centre=138.0, bw=SUBBAND_
 WORKLOADS = {w.name: w for w in (TINY, LOFAR)}
 
 
+@dataclass(frozen=True)
+class BeamDraw:
+    """One beam of the batched workload: its own subband count and centre,
+    N_bin (with n_c = N_bin / 4096, so every beam has M_bin = 4096), DM range
+    and trial count.  The overlap follows from the beam's lowest channel and
+    largest DM (Sec. 2), the block count from about one second of data."""
+    nsub: int
+    f_centre: float
+    nfft: int
+    nchan: int
+    ndec: int
+    dm_max: float
+    ndm: int
+
+    @property
+    def dms(self) -> tuple:
+        step = self.dm_max / (self.ndm - 1)
+        return tuple(float(i * step) for i in range(self.ndm))
+
+    @property
+    def f_lo(self) -> float:
+        return self.f_centre - self.nsub * SUBBAND_MHZ / 2
+
+
+def batch_draws(nbeam: int = 24, seed: int = 1607) -> list:
+    """Batched workload (several tied-array beams, Sec. 4): 32-288 subbands
+    inside 110-190 MHz, N_bin from {2^14, 2^15, 2^16, 2^17}, 16-256 DM trials
+    from 0 to a beam-specific maximum in [20, 200]."""
+    g = np.random.default_rng(np.random.SeedSequence([seed, 7331]))
+    out = []
+    for _ in range(nbeam):
+        nsub = int(g.integers(32, 289))
+        nfft = int(2 ** int(g.integers(14, 18)))
+        half = nsub * SUBBAND_MHZ / 2
+        f_centre = float(g.uniform(110.0 + half, 190.0 - half))
+        out.append(BeamDraw(nsub, f_centre, nfft, nfft // 4096, 8,
+                            float(g.uniform(20.0, 200.0)), int(g.integers(16, 257))))
+    return out
+
+
 def subband_rng(seed: int, s: int) -> np.random.Generator:
     """Independent stream per subband, so any subset regenerates alone."""
     return np.random.default_rng(np.random.SeedSequence([seed, s]))

@@ -148,3 +148,68 @@ def test_batch_graph_replays_and_autotune(hip_lib):
         ref = _single(hip_lib, sp, b[2], tile)
         torch.cuda.synchronize()
         assert torch.equal(b[4], ref), f"beam {i} after autotune"
+
+
+def test_batch_24_beam_workload(hip_lib):
+    """The benchmark's batched workload at full size (24 beams, ~125 GB), in
+    the benchmark's launch form (autotuned, graph replay): every output written
+    and finite, one (subband, block) pair per beam against the oracle, and two
+    beams bitwise equal to their single-beam runs."""
+    torch = _torch()
+    import math
+    from concurrent.futures import ThreadPoolExecutor
+    draws = synth.batch_draws()
+    print(f"[gpu-case] batch workload, {len(draws)} beams", flush=True)
+    beams, cfgs = [], []
+    for i, d in enumerate(draws):
+        # overlap from the oracle's Eq. 2 sweep over the lowest channel, rounded
+        # up to a multiple of 2 n_c ndec (as the plan helper does)
+        chan = synth.SUBBAND_MHZ / d.nchan
+        td = oracle.sweep_seconds(d.f_lo, d.f_lo + chan, d.dm_max)
+        q = 2 * d.nchan * d.ndec
+        nov = int(math.ceil(td * synth.SUBBAND_MHZ * 1e6 / q)) * q
+        assert nov == hip_lib.cdmt_noverlap_for(d.f_lo, synth.SUBBAND_MHZ, d.dm_max, d.nchan,
+                                                d.ndec, hip_lib.CHIRP_CHANNEL)
+        nblock = math.ceil(synth.SUBBAND_MHZ * 1e6 / (d.nfft - nov))
+        plan = hip_lib.Plan(d.nsub, d.f_centre, synth.SUBBAND_MHZ, d.nfft, nov, d.nchan, d.ndec,
+                            input_kind=hip_lib.INPUT_CI8)
+        ntin, ntout, nch = plan.shape(nblock)
+        x = synth.device_noise("ci8", d.nsub, ntin, 16.0, 1607 + i, "cuda")
+        out = torch.full((d.ndm, ntout, nch), float("nan"), device="cuda")
+        beams.append((plan, nblock, x, list(d.dms), out))
+        cfgs.append((d, nov, nblock))
+    batch = hip_lib.Batch(beams)
+    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == 1
+    stream = torch.cuda.Stream()
+    batch.autotune(stream, reps=1)
+    batch.run_graph(stream)
+    stream.synchronize()
+    for i, b in enumerate(beams):
+        assert bool(torch.isfinite(b[4]).all()), f"beam {i} not fully written"
+
+    def check(i):
+        d, nov, nblock = cfgs[i]
+        s, blk = (7 * i) % d.nsub, (3 * i) % nblock
+        xs = beams[i][2][s].cpu().numpy()[None]
+        c1 = oracle.Config(1, d.f_centre + (s - (d.nsub - 1) / 2) * synth.SUBBAND_MHZ,
+                           synth.SUBBAND_MHZ, d.nfft, nov, d.nchan, d.ndec)
+        want = oracle.subband_block(c1, xs, 0, blk, list(d.dms))
+        tb = want.shape[1]
+        cols = [(d.nsub - 1 - s) * d.nchan + (d.nchan - 1 - c) for c in range(d.nchan)]
+        got = beams[i][4][:, blk * tb:(blk + 1) * tb, cols].double().cpu().numpy()
+        dd = got - want
+        return float(np.sqrt((dd ** 2).sum((1, 2)) / (want ** 2).sum((1, 2))).max())
+
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        errs = list(ex.map(check, range(len(beams))))
+    print(f"batch workload vs oracle: worst beam {max(errs):.2e}", flush=True)
+    assert max(errs) <= 1e-5
+    tile = batch.get(hip_lib.CDMT_BATCH_DM_TILE)
+    for i in (0, len(beams) - 1):
+        d, nov, nblock = cfgs[i]
+        plan = hip_lib.Plan(d.nsub, d.f_centre, synth.SUBBAND_MHZ, d.nfft, nov, d.nchan, d.ndec,
+                            input_kind=hip_lib.INPUT_CI8, dm_tile=tile)
+        ref = plan.dedisperse(beams[i][2], nblock, list(d.dms))
+        torch.cuda.synchronize()
+        assert torch.equal(ref, beams[i][4]), f"beam {i} differs from its single-beam run"
+        del ref
