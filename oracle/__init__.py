@@ -72,6 +72,8 @@ def _load():
             lib.orc_tblk.argtypes = [ctypes.POINTER(_Cfg)]
             lib.orc_subband_block.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
                                               ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
+            lib.orc_dm_gradient.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
+                                            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P]
             lib.orc_dedisperse.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
                                            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int]
             lib.orc_inject_impulse.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
@@ -190,6 +192,26 @@ def subband_block(cfg: Config, x: np.ndarray, s: int, b: int, dms) -> np.ndarray
                                    out.ctypes.data)
     if st != 0:
         raise ValueError(f"orc_subband_block failed ({st})")
+    return out
+
+
+def dm_gradient(cfg: Config, x: np.ndarray, s: int, b: int, dms, G: np.ndarray) -> np.ndarray:
+    """d/dDM of L = sum G * F over one subband s and block b, one value per DM
+    (F and G as [ndm][tblk][nchan] in increasing channel frequency): the
+    adjoint of the per-DM chain of Sec. 3 (chirp of Eq. 1, swap, backward FFT,
+    detection, downsampling), each step's adjoint written out in the C file."""
+    x = _as_voltages(x)
+    dms = np.ascontiguousarray(dms, dtype=np.float64)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    if G.shape != (dms.size, cfg.tblk, cfg.nchan):
+        raise ValueError("G must be [ndm][tblk][nchan]")
+    xs = np.ascontiguousarray(x[s])
+    out = np.empty(dms.size, dtype=np.float64)
+    st = _load().orc_dm_gradient(ctypes.byref(cfg.c()), _kind_of(xs), xs.ctypes.data,
+                                 xs.shape[0], s, b, dms.ctypes.data, dms.size,
+                                 G.ctypes.data, out.ctypes.data)
+    if st != 0:
+        raise ValueError(f"orc_dm_gradient failed ({st})")
     return out
 
 

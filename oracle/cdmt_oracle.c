@@ -307,6 +307,90 @@ typedef struct {
     pthread_mutex_t mu;
 } orc_job;
 
+/*
+ * Derivative with respect to DM of L = sum_{d,t,ch} G[d][t][ch] F[d][t][ch]
+ * for one subband s and block b, one value per DM trial (F as produced by
+ * orc_subband_block, G in the same layout).  Not a step of the paper: the
+ * adjoint of its per-DM chain, for refining a candidate's DM by gradient
+ * ascent.  Each forward step of orc_subband_block is followed, then its
+ * adjoint in reverse order (complex gradients as dL = Re sum conj(g) dv):
+ *   F = sum of ndec kept samples of I       -> dL/dI[i] = G[t(i)] (0 if dropped)
+ *   I = |y_X|^2 + |y_Y|^2                   -> g_y = 2 (dL/dI) y
+ *   y = backward transform (e^{+}) of z     -> g_z = forward transform (e^{-}) of g_y
+ *   z = channel-swapped S' (a permutation)  -> g_S' = the inverse permutation of g_z
+ *   S'_j = S_j h_j, h_j = exp(sign 2 pi i Phi_j) / N, Phi_j = DM phi_j (Eq. 1
+ *   is linear in DM)                        -> dS'_j/dDM = sign 2 pi i phi_j S'_j
+ *   dL/dDM = sum_j Re(conj(g_S'_j) dS'_j/dDM), both polarisations.
+ */
+int orc_dm_gradient(const orc_cfg *c, int kind, const void *x_sub, long ntime, int s, int b,
+                    const double *dms, int ndm, const double *G, double *dldm)
+{
+    if (orc_validate(c))
+        return -1;
+    const long n = c->nfft, m = n / c->nchan;
+    const long nd = c->noverlap / c->nchan;
+    const long tb = (m - nd) / c->ndec;
+    const long start = (long)b * (n - c->noverlap);
+    if (start + n > ntime)
+        return -2;
+
+    cplx *spec = (cplx *)malloc(sizeof(cplx) * 2 * n);
+    cplx *seg = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *z = (cplx *)malloc(sizeof(cplx) * 2 * m);
+    cplx *h = (cplx *)malloc(sizeof(cplx) * n);
+    double *phi = (double *)malloc(sizeof(double) * n);
+    double *gi = (double *)malloc(sizeof(double) * m);
+    if (!spec || !seg || !z || !h || !phi || !gi) {
+        free(spec); free(seg); free(z); free(h); free(phi); free(gi);
+        return -3;
+    }
+    for (int p = 0; p < 2; ++p) {
+        for (long i = 0; i < n; ++i)
+            seg[i] = load_sample(kind, x_sub, start + i, p);
+        orc_fft_inplace(seg, n, -1);
+        for (long j = 0; j < n; ++j)
+            spec[p * n + j] = seg[(j + n / 2) % n];
+    }
+    for (long j = 0; j < n; ++j) {
+        double nu0, nu;
+        bin_frequency(c, s, j, n, &nu0, &nu);
+        phi[j] = orc_chirp_cycles(nu, nu0, 1.0);          /* Eq. 1 cycles per unit DM */
+    }
+    for (int d = 0; d < ndm; ++d) {
+        for (long j = 0; j < n; ++j)
+            h[j] = cexp(I * (double)c->sign * 2.0 * ORC_PI * phi[j] * dms[d]) / (double)n;
+        double acc = 0.0;
+        for (long ch = 0; ch < c->nchan; ++ch) {
+            /* dL/dI over the channel's M samples */
+            for (long i = 0; i < m; ++i)
+                gi[i] = 0.0;
+            for (long t = 0; t < tb; ++t)
+                for (long q = 0; q < c->ndec; ++q)
+                    gi[nd / 2 + t * c->ndec + q] = G[((long)d * tb + t) * c->nchan + ch];
+            for (int p = 0; p < 2; ++p) {
+                cplx *zp = z + p * m;
+                for (long i = 0; i < m; ++i) {
+                    long j = ch * m + (i + m / 2) % m;
+                    zp[i] = spec[p * n + j] * h[j];
+                }
+                orc_fft_inplace(zp, m, +1);                 /* y */
+                for (long i = 0; i < m; ++i)
+                    zp[i] = 2.0 * gi[i] * zp[i];             /* g_y */
+                orc_fft_inplace(zp, m, -1);                 /* g_z */
+                for (long i = 0; i < m; ++i) {
+                    long j = ch * m + (i + m / 2) % m;       /* g_S' at bin j */
+                    cplx sp = spec[p * n + j] * h[j];
+                    cplx ds = (double)c->sign * 2.0 * ORC_PI * phi[j] * I * sp;
+                    acc += creal(conj(zp[i]) * ds);
+                }
+            }
+        }
+        dldm[d] = acc;
+    }
+    free(spec); free(seg); free(z); free(h); free(phi); free(gi);
+    return 0;
+}
+
 static size_t sample_bytes(int kind)
 {
     return kind == ORC_CI8 ? 4 : (kind == ORC_CF32 ? 16 : 32);

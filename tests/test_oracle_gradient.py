@@ -1,0 +1,87 @@
+"""Pins of the oracle's DM gradient (the adjoint of the per-DM chain of Sec. 3:
+transfer function of Eq. 1, swap, backward FFT, detection, downsampling).
+
+The adjoint is checked against what fixes it independently of its own code:
+central finite differences of the oracle's forward filterbank (step 1e-4 pc
+cm^-3, as for candidate refinement), a pure tone (whose channelised power does
+not depend on DM, so the derivative vanishes), an impulse dispersed at DM0
+(whose recompressed peak is a maximum at DM0: positive slope below, negative
+above, ~0 at DM0), and linearity in the upstream gradient."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1607_00909_amd import synth
+
+H = 1e-4
+
+
+def _cfg(mode):
+    # 2 subbands at 120 MHz, N_bin 4096 / noverlap 1024, 4 channels (M 1024), ndec 4
+    return oracle.Config(2, 120.0, synth.SUBBAND_MHZ, 4096, 1024, 4, 4, chirp_ref=mode)
+
+
+def _loss(cfg, x, s, b, dm, G):
+    F = oracle.subband_block(cfg, x, s, b, [dm])
+    return float((F * G).sum())
+
+
+@pytest.mark.parametrize("mode", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
+def test_gradient_matches_central_differences(mode):
+    cfg = _cfg(mode)
+    x = synth.gaussian_voltages(cfg.nsub, cfg.ntime_in(2), 1.0, 11)
+    oracle.inject_impulse(cfg, x, 1, 10.0, oracle.pulse_sample(cfg, cfg.tblk + 40), 30.0)
+    g = np.random.default_rng(3).standard_normal((1, cfg.tblk, cfg.nchan))
+    def cd(s, b, dm, h):
+        return (_loss(cfg, x, s, b, dm + h, g) - _loss(cfg, x, s, b, dm - h, g)) / (2 * h)
+
+    for dm in (3.7, 9.9, 10.0, 12.3, 40.0):
+        for s, b in ((0, 0), (1, 1)):
+            an = oracle.dm_gradient(cfg, x, s, b, [dm], g)[0]
+            # central differences at 1e-4 and 5e-5, Richardson-combined (error O(h^4))
+            fd = (4.0 * cd(s, b, dm, H / 2) - cd(s, b, dm, H)) / 3.0
+            scale = abs(_loss(cfg, x, s, b, dm, np.abs(g)))
+            assert abs(an - fd) <= 1e-7 * (abs(fd) + 1e-3 * scale), (dm, s, b, an, fd)
+
+
+def test_gradient_of_a_pure_tone_vanishes():
+    cfg = _cfg(oracle.CHANNEL)
+    n = cfg.ntime_in(1)
+    k = 1500                                       # a tone on bin 1500 of the 4096-point grid
+    t = np.arange(n)
+    tone = np.exp(2j * np.pi * k * t / cfg.nfft)
+    x = np.stack([tone, 0.5 * tone], axis=-1)[None].repeat(cfg.nsub, axis=0).copy()
+    g = np.random.default_rng(4).standard_normal((3, cfg.tblk, cfg.nchan))
+    grad = oracle.dm_gradient(cfg, x, 0, 0, [0.0, 17.0, 55.5], g)
+    scale = np.abs(oracle.subband_block(cfg, x, 0, 0, [0.0])).sum() * np.abs(g).max()
+    assert np.all(np.abs(grad) <= 1e-12 * scale), grad
+
+
+@pytest.mark.parametrize("mode", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
+def test_recompressed_impulse_is_a_maximum_at_its_dm(mode):
+    cfg = _cfg(mode)
+    x = np.zeros((cfg.nsub, cfg.ntime_in(1), 2), dtype=np.complex128)
+    t0 = cfg.tblk // 2
+    # DM 3 keeps even the subband-wide sweep (~550 samples) inside the overlap
+    dm0 = 3.0
+    oracle.inject_impulse(cfg, x, 0, dm0, oracle.pulse_sample(cfg, t0), 1.0)
+    G = np.zeros((1, cfg.tblk, cfg.nchan))
+    G[0, t0, :] = 1.0                              # L = channel sum at the pulse sample
+    at = oracle.dm_gradient(cfg, x, 0, 0, [dm0], G)[0]
+    lo = oracle.dm_gradient(cfg, x, 0, 0, [dm0 - 1.0], G)[0]
+    hi = oracle.dm_gradient(cfg, x, 0, 0, [dm0 + 1.0], G)[0]
+    assert lo > 0 > hi
+    assert abs(at) <= 1e-3 * max(abs(lo), abs(hi))
+
+
+def test_gradient_is_linear_in_the_upstream_gradient():
+    cfg = _cfg(oracle.SUBBAND)
+    x = synth.gaussian_voltages(cfg.nsub, cfg.ntime_in(1), 1.0, 12)
+    r = np.random.default_rng(5)
+    g1 = r.standard_normal((2, cfg.tblk, cfg.nchan))
+    g2 = r.standard_normal((2, cfg.tblk, cfg.nchan))
+    dms = [4.0, 31.0]
+    a = oracle.dm_gradient(cfg, x, 1, 0, dms, g1)
+    b = oracle.dm_gradient(cfg, x, 1, 0, dms, g2)
+    c = oracle.dm_gradient(cfg, x, 1, 0, dms, 2.0 * g1 - 3.0 * g2)
+    assert np.allclose(c, 2.0 * a - 3.0 * b, rtol=1e-10, atol=1e-12 * np.abs(c).max())

@@ -13,6 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "cdmt_oracle.c")
 PINS = os.path.join(ROOT, "tests", "test_oracle_pins.py")
+GRAD_PINS = os.path.join(ROOT, "tests", "test_oracle_gradient.py")
 
 # (description, exact source text, replacement)
 MUTANTS = [
@@ -35,11 +36,25 @@ MUTANTS = [
     ("FFT twiddle sign", "double a = sign * 2.0 * ORC_PI * (double)k / (double)len;",
      "double a = -sign * 2.0 * ORC_PI * (double)k / (double)len;"),
 ]
+# mistakes in the DM gradient, each of which the gradient pins must catch
+GRAD_MUTANTS = [
+    ("gradient: detection factor 2 dropped", "zp[i] = 2.0 * gi[i] * zp[i];", "zp[i] = gi[i] * zp[i];"),
+    ("gradient: adjoint transform with e^+", "orc_fft_inplace(zp, m, -1);", "orc_fft_inplace(zp, m, +1);"),
+    ("gradient: derivative of Eq. 1 with the wrong sign", "cplx ds = (double)c->sign * 2.0",
+     "cplx ds = -(double)c->sign * 2.0"),
+    ("gradient: upstream gradient without the unpad offset",
+     "gi[nd / 2 + t * c->ndec + q] = G[", "gi[t * c->ndec + q] = G["),
+    ("gradient: imaginary part taken", "acc += creal(conj(zp[i]) * ds);",
+     "acc += cimag(conj(zp[i]) * ds);"),
+    ("gradient: channel swap not inverted", "long j = ch * m + (i + m / 2) % m;       /* g_S' at bin j */",
+     "long j = ch * m + i;"),
+    ("gradient: one polarisation", "cplx *zp = z + p * m;", "cplx *zp = z + p * m; if (p) continue;"),
+]
 EQUIVALENT = ("no swap of halves per channel", "long j = ch * m + (i + m / 2) % m;",
               "long j = ch * m + i;")
 
 
-def _build_and_run(tmp_path, name, old, new):
+def _build_and_run(tmp_path, name, old, new, pins=PINS):
     src = open(SRC).read()
     assert src.count(old) >= 1, f"pattern for '{name}' not found"
     mut = src.replace(old, new, 1)
@@ -49,7 +64,7 @@ def _build_and_run(tmp_path, name, old, new):
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", str(c), "-o", str(so),
                            "-lm", "-lpthread"])
     env = dict(os.environ, CDMT_ORACLE_LIB=str(so))
-    r = subprocess.run([sys.executable, "-m", "pytest", PINS, "-q", "-x", "-p", "no:cacheprovider"],
+    r = subprocess.run([sys.executable, "-m", "pytest", pins, "-q", "-x", "-p", "no:cacheprovider"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode
 
@@ -64,3 +79,10 @@ def test_pins_kill_mutant(tmp_path, name, old, new):
 def test_channel_half_swap_is_invisible_after_detection(tmp_path):
     name, old, new = EQUIVALENT
     assert _build_and_run(tmp_path, name, old, new) == 0
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not available")
+@pytest.mark.parametrize("name,old,new", GRAD_MUTANTS, ids=[m[0] for m in GRAD_MUTANTS])
+def test_gradient_pins_kill_mutant(tmp_path, name, old, new):
+    assert _build_and_run(tmp_path, name, old, new, GRAD_PINS) != 0, \
+        f"mutant '{name}' survived the gradient pins"
