@@ -172,6 +172,55 @@ def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
     return res
 
 
+def gradient_leg(cdmt, synth, torch, dev, steps: int):
+    """dL/dDM for 64 candidate DMs on a 1 s segment of the LOFAR-shaped setup
+    (288 subbands, complex float32 input, N_bin 65536): the forward DM stage
+    at the candidates plus the adjoint, as one refinement step costs."""
+    import ctypes as ct
+    import math
+    w = synth.LOFAR
+    nblock = math.ceil(synth.SUBBAND_MHZ * 1e6 / (w.nfft - w.noverlap))
+    plan = cdmt.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                     input_kind=cdmt.INPUT_CF32, chirp_exact=1)
+    ntin, ntout, nch = plan.shape(nblock)
+    x = synth.device_noise("cf32", w.nsub, ntin, 1.0, 4242, dev)
+    ws = plan.workspace(nblock, dev)
+    plan.forward(x, nblock, ws)
+    dms = [5.0 + 0.73 * i for i in range(64)]           # off-grid candidates
+    out = torch.empty((len(dms), ntout, nch), dtype=torch.float32, device=dev)
+    g = torch.randn((len(dms), ntout, nch), dtype=torch.float32, device=dev)
+    gws = torch.empty(max(1, cdmt.cdmt_gradient_workspace_size(plan.handle, nblock, len(dms))),
+                      dtype=torch.uint8, device=dev)
+    dldm = torch.empty(len(dms), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def grad():
+        cdmt.cdmt_dm_gradient(plan.handle, ct.c_void_p(ws.data_ptr()), ws.numel(), nblock, dms,
+                              ct.c_void_p(g.data_ptr()), ct.c_void_p(gws.data_ptr()), gws.numel(),
+                              ct.c_void_p(dldm.data_ptr()), ct.c_void_p(stream.cuda_stream))
+
+    plan.dedisperse_spectra(nblock, dms, out, ws)
+    grad()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        plan.dedisperse_spectra(nblock, dms, out, ws)
+    ev[1].record(stream)
+    for _ in range(steps):
+        grad()
+    ev[2].record(stream)
+    torch.cuda.synchronize()
+    fwd = ev[0].elapsed_time(ev[1]) / steps
+    adj = ev[1].elapsed_time(ev[2]) / steps
+    data_s = cdmt.dm_seconds(nblock, w.nfft, w.noverlap, w.bw)
+    log(f"gradient: 64 candidates, forward {fwd:.3f} ms, adjoint {adj:.3f} ms")
+    return {"workload": f"gradient-{w.nsub}sub-64dm-1s", "candidates": len(dms),
+            "data_seconds": round(data_s, 4), "forward_ms": round(fwd, 3),
+            "gradient_ms": round(adj, 3),
+            "gradient_dm_s_per_s": round(len(dms) * data_s / (adj / 1e3), 1)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,6 +236,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the other DM-stage arithmetics (mixed vs FP32 plain)")
+    ap.add_argument("--gradient", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time dL/dDM for 64 candidate DMs on a 1 s segment")
     ap.add_argument("--batch", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 24-beam batched workload (persistent launch, hipGraph)")
     ap.add_argument("--redigitise", action=argparse.BooleanOptionalAction, default=True,
@@ -383,6 +434,10 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
         line["batch"] = batch_leg(cdmt, synth, torch, dev, args.steps, 1)
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    if args.gradient:
+        line["gradient"] = gradient_leg(cdmt, synth, torch, dev, args.steps)
     print(json.dumps(line), flush=True)
 
 

@@ -146,6 +146,30 @@ int cdmt_dedisperse(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const vo
                     int nblock, const double *dm_list, int ndm, float *out, void *hip_stream);
 
 /*
+ * Derivative with respect to DM, for refining a candidate's DM by gradient
+ * ascent (an extension beyond the paper: the adjoint of the DM stage of
+ * Alg. 1).  For the spectra left by cdmt_forward and DM trials dm_list, with
+ * the caller's upstream gradient grad_out = dL/dF of a scalar loss L of the
+ * filterbank F that cdmt_dedisperse_spectra would produce with the exact
+ * transfer function (CDMT_OPT_CHIRP_EXACT = 1):
+ *   dldm[d] = dL/dDM_d = sum over subbands, blocks, channels and pols of
+ *             Re(conj(g) i pi g2 S'), g the back-propagated gradient of the
+ *             chirped spectrum S' (through detection, the downsampling sum and
+ *             the backward FFT; the complex time series are recomputed, not
+ *             stored), pi g2 = d(phase)/dDM of Eq. 1.
+ *   grad_out  device float32 [ndm][ntime_out][nchan_out] (layout of the output)
+ *   dldm      device float64 [ndm]
+ *   gws       device, >= cdmt_gradient_workspace_size bytes (FP64 partial
+ *             sums, 8 bytes per DM per 4096-bin chunk group)
+ * FP32 arithmetic with FP64 accumulation; M_bin <= 4096 (CDMT_E_UNSUPPORTED
+ * otherwise).  Asynchronous on hip_stream; on error nothing is written.
+ */
+int cdmt_gradient_workspace_size(cdmt_plan_t plan, int nblock, int ndm, size_t *bytes);
+int cdmt_dm_gradient(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nblock,
+                     const double *dm_list, int ndm, const float *grad_out, void *gws,
+                     size_t gws_bytes, double *dldm, void *hip_stream);
+
+/*
  * Redigitisation of a filterbank to 8-bit codes (Sec. 3, the paragraph after
  * the transpose; Alg. 1 "redigitize").  Independent of any plan: it takes any
  * FP32 filterbank [ndm][ntime][nchan], e.g. the output of cdmt_dedisperse.

@@ -33,7 +33,8 @@ EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
            "cdmt_dedisperse_spectra", "cdmt_dedisperse", "cdmt_destroy", "cdmt_status_string",
            "cdmt_redigitise_workspace_size", "cdmt_redigitise",
            "cdmt_batch_workspace_size", "cdmt_batch_create", "cdmt_batch_set", "cdmt_batch_get",
-           "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy")
+           "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy",
+           "cdmt_gradient_workspace_size", "cdmt_dm_gradient")
 # enum cdmt_batch_opt
 CDMT_BATCH_DM_TILE, CDMT_BATCH_WG_PER_CU, CDMT_BATCH_ITEMS, CDMT_BATCH_LAUNCHES = 0, 1, 2, 3
 
@@ -87,6 +88,8 @@ def load():
         F = ctypes.c_float
         lib.cdmt_redigitise_workspace_size.argtypes = [I, LL, I, ctypes.POINTER(Z)]
         lib.cdmt_redigitise.argtypes = [P, I, LL, I, F, F, P, Z, P, P, P, P]
+        lib.cdmt_gradient_workspace_size.argtypes = [P, I, I, ctypes.POINTER(Z)]
+        lib.cdmt_dm_gradient.argtypes = [P, P, Z, I, ctypes.POINTER(D), I, P, P, Z, P, P]
         BP = ctypes.POINTER(Beam)
         lib.cdmt_batch_workspace_size.argtypes = [BP, I, ctypes.POINTER(Z)]
         lib.cdmt_batch_create.argtypes = [ctypes.POINTER(P), BP, I, P, Z]
@@ -215,6 +218,69 @@ def redigitise(fb, zero=64.0, counts_per_sigma=16.0, workspace=None, stream=None
                     ctypes.c_void_p(mean.data_ptr()), ctypes.c_void_p(scale.data_ptr()),
                     ctypes.c_void_p(s.cuda_stream))
     return codes, mean, scale
+
+
+def cdmt_gradient_workspace_size(plan, nblock, ndm) -> int:
+    v = ctypes.c_size_t()
+    _check(load().cdmt_gradient_workspace_size(plan, nblock, ndm, ctypes.byref(v)),
+           "cdmt_gradient_workspace_size")
+    return v.value
+
+
+def cdmt_dm_gradient(plan, workspace, ws_bytes, nblock, dms, grad_out, gws, gws_bytes, dldm,
+                     stream) -> None:
+    arr, n = _dm_array(dms)
+    _check(load().cdmt_dm_gradient(plan, workspace, ws_bytes, nblock, arr, n, grad_out, gws,
+                                   gws_bytes, dldm, stream), "cdmt_dm_gradient")
+
+
+def _dm_stage_function():
+    import torch
+
+    class DMStage(torch.autograd.Function):
+        """F = the DM stage of Alg. 1 at the (continuous) trial DMs in a tensor;
+        backward returns dL/dDM through cdmt_dm_gradient.  The spectra must
+        already be in the workspace (Plan.forward) and the plan should use the
+        exact transfer function (chirp_exact=1), the form the gradient is of."""
+
+        @staticmethod
+        def forward(ctx, dms, plan, nblock, workspace):
+            dm_list = [float(v) for v in dms.detach().cpu().tolist()]
+            _, ntout, nch = plan.shape(nblock)
+            out = torch.empty((len(dm_list), ntout, nch), dtype=torch.float32,
+                              device=workspace.device)
+            plan.dedisperse_spectra(nblock, dm_list, out, workspace)
+            ctx.plan, ctx.nblock, ctx.ws, ctx.dm_list = plan, nblock, workspace, dm_list
+            ctx.dms_device, ctx.dms_dtype = dms.device, dms.dtype
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = grad_out.detach().to(torch.float32).contiguous()
+            n = len(ctx.dm_list)
+            dldm = torch.empty(n, dtype=torch.float64, device=g.device)
+            gsz = cdmt_gradient_workspace_size(ctx.plan.handle, ctx.nblock, n)
+            gws = torch.empty(max(1, gsz), dtype=torch.uint8, device=g.device)
+            cdmt_dm_gradient(ctx.plan.handle, ctypes.c_void_p(ctx.ws.data_ptr()), ctx.ws.numel(),
+                             ctx.nblock, ctx.dm_list, ctypes.c_void_p(g.data_ptr()),
+                             ctypes.c_void_p(gws.data_ptr()), gws.numel(),
+                             ctypes.c_void_p(dldm.data_ptr()),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            return dldm.to(ctx.dms_device, ctx.dms_dtype), None, None, None
+
+    return DMStage
+
+
+def dedisperse_dm(plan, dms, nblock, workspace):
+    """Differentiable DM stage: filterbank [ndm][ntime_out][nchan_out] at the DMs
+    of the tensor dms (requires_grad for dL/dDM)."""
+    global _DMStage
+    if _DMStage is None:
+        _DMStage = _dm_stage_function()
+    return _DMStage.apply(dms, plan, nblock, workspace)
+
+
+_DMStage = None
 
 
 def cdmt_batch_workspace_size(beams, nbeam) -> int:
@@ -397,4 +463,4 @@ def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
 
 __all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
                                                           "dm_seconds", "redigitise", "Batch",
-                                                          "Beam", "EXPORTS"]
+                                                          "Beam", "dedisperse_dm", "EXPORTS"]

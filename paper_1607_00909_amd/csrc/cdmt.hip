@@ -846,6 +846,130 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
 }
 
 // ---------------------------------------------------------------------------
+// Derivative with respect to DM of L = sum G * F (G = dL/dF given by the
+// caller for every filterbank sample), for refining a candidate's DM: the
+// adjoint of the per-DM chain, each step reversed in turn.  Per chunk and
+// DM, with S' = S H the chirped spectrum (exact transfer function, H =
+// exp(i pi DM g2)):
+//   y = backward FFT of swap(S')            (forward pass, kept in registers)
+//   g_y = 2 (dL/dI) y, dL/dI[m] = G at the output sample holding m (0 on
+//         the discarded edges)              (detection and downsampling)
+//   g_z = forward FFT (e^{-}) of g_y        (adjoint of the e^{+} transform)
+//   dL/dDM = sum Re(conj(g_S') i pi g2 S'), g_S' = unswap(g_z), both pols.
+// One workgroup per (chunk group, DM); FP64 partial sums per workgroup,
+// reduced per DM in a fixed order by dm_grad_sum (deterministic).
+template <int M>
+__global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
+                                                  const float *__restrict__ gout,
+                                                  double *__restrict__ part, long long ncg_all,
+                                                  int dm_first) {
+    using Sh = FusedShape<M, 16>;
+    constexpr int R = 16;
+    constexpr int T = Sh::T;
+    constexpr int C = Sh::C;
+    constexpr int STRIDE = Sh::STRIDE;
+    static_assert(Sh::WG == 256, "256-lane workgroups");
+    __shared__ cpair sh[C * STRIDE];
+    __shared__ double red[4];
+
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int d = lw % a.ndm;
+    const int cg = a.cg0 + lw / a.ndm;
+    const int t = threadIdx.x;
+    const int f = t / T, tt = t % T;
+    const int chunk = cg * C + f;
+    const bool valid = chunk < a.nchunks;
+    const int cc = valid ? chunk : 0;
+    const int c = cc % a.nchan;
+    const int bs = cc / a.nchan;
+    const int s = bs % a.nsub;
+    const int b = bs / a.nsub;
+
+    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
+    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
+    double nu0, off;
+    if (a.chirp_ref == 0) {
+        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
+        off = -0.5 * M;
+    } else {
+        nu0 = fs;
+        off = (double)c * M - 0.5 * a.n;
+    }
+    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
+    const double dm = dl.dm[d];
+    double g2[R];
+    cpair sp[R], v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const double nu = ((double)(tt + T * q) + off) * a.delta;
+        g2[q] = scale * nu * nu / (nu0 + nu);
+        const double ph = dm * g2[q];
+        const double n = rint(ph);
+        float sn, cs;
+        sincos_pi(static_cast<float>(ph - n), sn, cs);
+        const int flip = static_cast<int>(n) << 31;
+        sn = __int_as_float(__float_as_int(sn) ^ flip);
+        cs = __int_as_float(__float_as_int(cs) ^ flip);
+        const cpair r = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        sp[q] = cdmt::pmul(r, make_float2(cs, sn));
+        v[q ^ (R / 2)] = sp[q];
+    }
+    const cdmt::LdsPad<R> lds{sh + f * STRIDE};
+    cdmt::wg_fft<M, +1>(v, tt, lds);               // y, sample m = tt + T q
+
+    const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
+    const float *g = gout + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + col;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int m = tt + T * q;
+        float gi = 0.f;
+        if (valid && m >= a.nd_half && m < M - a.nd_half)
+            gi = g[(long long)((m - a.nd_half) / a.ndec) * a.nch_out];
+        v[q] = cdmt::pscale(v[q], 2.0f * gi);
+    }
+    __syncthreads();                               // the first transform's LDS reads are done
+    cdmt::wg_fft<M, -1>(v, tt, lds);               // g_z, bin j = tt + T q
+
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const cpair gz = v[q ^ (R / 2)];           // g_S' of this lane's bin q
+        const cpair x = sp[q];
+        const float tx = gz.y * x.x - gz.x * x.y;  // Re(conj(g) i S'), pol X
+        const float ty = gz.w * x.z - gz.z * x.w;  // pol Y
+        acc = fma(g2[q], (double)tx + (double)ty, acc);
+    }
+    if (!valid)
+        acc = 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        acc += __shfl_xor(acc, o);
+    if ((t & 63) == 0)
+        red[t >> 6] = acc;
+    __syncthreads();
+    if (t == 0)
+        part[(long long)(dm_first + d) * ncg_all + cg] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// dL/dDM[d] = pi * sum over chunk groups of the partials, fixed order
+__global__ __launch_bounds__(256) void dm_grad_sum(const double *__restrict__ part, long long ncg,
+                                                   double *__restrict__ dldm) {
+    __shared__ double red[4];
+    const int d = blockIdx.x;
+    double acc = 0.0;
+    for (long long i = threadIdx.x; i < ncg; i += 256)
+        acc += part[(long long)d * ncg + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        acc += __shfl_xor(acc, o);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        dldm[d] = M_PI * ((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+// ---------------------------------------------------------------------------
 // Batches: several beams, each with its own plan (subbands, N_bin, channels,
 // overlap), input, DM list and output, through the FP32 DM stage in one
 // persistent launch per M_bin present and per form of the transfer function
@@ -1148,6 +1272,37 @@ int launch_dedisperse(const cdmt_plan_s *p, void *ws, int nblock, const double *
     }
 }
 
+template <int M>
+int launch_grad_m(const FusedArgs &a0, const double *dms, int ndm, const float *gout, double *part,
+                  long long ncg, double *dldm, hipStream_t st) {
+    constexpr long long kMaxGroups = 0xffffffffLL / 256;
+    for (int first = 0; first < ndm; first += kMaxDmPerLaunch) {
+        FusedArgs a = a0;
+        const int cnt = ndm - first < kMaxDmPerLaunch ? ndm - first : kMaxDmPerLaunch;
+        DmList dl;
+        std::memset(&dl, 0, sizeof(dl));
+        for (int i = 0; i < cnt; ++i)
+            dl.dm[i] = dms[first + i];
+        a.ndm = cnt;
+        const float *g = gout + (long long)first * a0.ntime_out * a0.nch_out;
+        const long long per = kMaxGroups / cnt;
+        for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
+            const long long n = ncg - cg0 < per ? ncg - cg0 : per;
+            a.cg0 = (int)cg0;
+            dm_grad<M><<<(unsigned)(n * cnt), 256, 0, st>>>(a, dl, g, part, ncg, first);
+            if (hipGetLastError() != hipSuccess)
+                return CDMT_E_DEVICE;
+        }
+    }
+    dm_grad_sum<<<ndm, 256, 0, st>>>(part, ncg, dldm);
+    return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
+}
+
+long long grad_groups(const cdmt_plan_s *p, int nblock) {
+    const int C = 4096 / p->m;
+    return ((long long)nblock * p->nsub * p->nchan + C - 1) / C;
+}
+
 int check_plan(const cdmt_plan_s *p) { return p ? CDMT_OK : CDMT_E_ARG; }
 
 
@@ -1362,12 +1517,62 @@ int cdmt_dedisperse(cdmt_plan_t p, void *ws, size_t ws_bytes, const void *voltag
         return CDMT_OK;
     if (!voltages || !dm_list || !out)
         return CDMT_E_ARG;
+    const double bound = max_half_cycles_per_dm(p);
     for (int i = 0; i < ndm; ++i)
-        if (!std::isfinite(dm_list[i]))
+        if (!std::isfinite(dm_list[i]) || std::fabs(dm_list[i]) * bound >= 1073741824.0)
             return CDMT_E_ARG;
     if ((st = cdmt_forward(p, ws, ws_bytes, voltages, nblock, hip_stream)))
         return st;
     return cdmt_dedisperse_spectra(p, ws, ws_bytes, nblock, dm_list, ndm, out, hip_stream);
+}
+
+int cdmt_gradient_workspace_size(cdmt_plan_t p, int nblock, int ndm, size_t *bytes) {
+    if (!p || !bytes || nblock < 0 || ndm < 0)
+        return CDMT_E_ARG;
+    if (p->m > 4096)
+        return CDMT_E_UNSUPPORTED;
+    *bytes = (size_t)ndm * (size_t)grad_groups(p, nblock) * sizeof(double);
+    return CDMT_OK;
+}
+
+int cdmt_dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const double *dm_list,
+                     int ndm, const float *grad_out, void *gws, size_t gws_bytes, double *dldm,
+                     void *hip_stream) {
+    int st = check_call(p, ws, ws_bytes, nblock);
+    if (st)
+        return st;
+    if (ndm < 0)
+        return CDMT_E_ARG;
+    if (p->m > 4096)
+        return CDMT_E_UNSUPPORTED;
+    if (ndm == 0 || nblock == 0)
+        return CDMT_OK;
+    if (!dm_list || !grad_out || !gws || !dldm)
+        return CDMT_E_ARG;
+    const double bound = max_half_cycles_per_dm(p);
+    for (int i = 0; i < ndm; ++i)
+        if (!std::isfinite(dm_list[i]) || std::fabs(dm_list[i]) * bound >= 1073741824.0)
+            return CDMT_E_ARG;
+    size_t need = 0;
+    cdmt_gradient_workspace_size(p, nblock, ndm, &need);
+    if (gws_bytes < need)
+        return CDMT_E_WORKSPACE;
+    if ((st = ensure_twiddles()))
+        return st;
+    const FusedArgs a = fused_args(p, ws, nblock, nullptr);
+    const long long ncg = grad_groups(p, nblock);
+    double *part = static_cast<double *>(gws);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    switch (p->m) {
+    case 64: return launch_grad_m<64>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 128: return launch_grad_m<128>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 256: return launch_grad_m<256>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 512: return launch_grad_m<512>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 1024: return launch_grad_m<1024>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 2048: return launch_grad_m<2048>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 4096: return launch_grad_m<4096>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    default: return CDMT_E_UNSUPPORTED;
+    }
 }
 
 void cdmt_destroy(cdmt_plan_t p) { delete p; }

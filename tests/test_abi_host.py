@@ -250,3 +250,32 @@ def test_batch_validation(lib):
     finally:
         for p in (p1, p2, p3):
             cdmt.cdmt_destroy(p)
+
+
+def test_gradient_validation(lib):
+    """cdmt_dm_gradient argument checks, returned before any device work."""
+    import ctypes
+    p = cdmt.cdmt_plan(*GOOD)                                    # M = 2048
+    p8 = cdmt.cdmt_plan(2, 120.0, 0.1953125, 65536, 4096, 8, 4)  # M = 8192
+    try:
+        z = ctypes.c_size_t()
+        assert lib.cdmt_gradient_workspace_size(p, 3, 5, ctypes.byref(z)) == cdmt.CDMT_OK
+        assert z.value == 5 * (3 * 8 * 8 // 2) * 8        # DMs x chunk groups (2 chunks each) x 8 B
+        assert lib.cdmt_gradient_workspace_size(p8, 1, 5, ctypes.byref(z)) == \
+            cdmt.CDMT_E_UNSUPPORTED
+        assert lib.cdmt_gradient_workspace_size(p, -1, 5, ctypes.byref(z)) == cdmt.CDMT_E_ARG
+        P = ctypes.c_void_p(256)
+        dm = (ctypes.c_double * 2)(1.0, 2.0)
+        g = lib.cdmt_dm_gradient
+        big = 1 << 40
+        assert g(p, P, big, 2, dm, 0, None, None, 0, None, None) == cdmt.CDMT_OK     # no-op
+        assert g(p, P, big, 2, dm, -1, P, P, big, P, None) == cdmt.CDMT_E_ARG
+        assert g(p, P, big, 2, dm, 2, None, P, big, P, None) == cdmt.CDMT_E_ARG
+        assert g(p, P, big, 2, dm, 2, P, P, 8, P, None) == cdmt.CDMT_E_WORKSPACE
+        assert g(p, P, 16, 2, dm, 2, P, P, big, P, None) == cdmt.CDMT_E_WORKSPACE
+        assert g(p8, P, big, 1, dm, 2, P, P, big, P, None) == cdmt.CDMT_E_UNSUPPORTED
+        bad = (ctypes.c_double * 2)(1.0, float("inf"))
+        assert g(p, P, big, 2, bad, 2, P, P, big, P, None) == cdmt.CDMT_E_ARG
+    finally:
+        cdmt.cdmt_destroy(p)
+        cdmt.cdmt_destroy(p8)
