@@ -74,6 +74,9 @@ def _load():
                                               ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
             lib.orc_dm_gradient.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
                                             ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P]
+            lib.orc_voltage_gradient.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P,
+                                                 ctypes.c_long, ctypes.c_int, ctypes.c_int,
+                                                 ctypes.c_double, P, P]
             lib.orc_dedisperse.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
                                            ctypes.c_int, P, ctypes.c_int, P, ctypes.c_int]
             lib.orc_inject_impulse.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
@@ -213,6 +216,29 @@ def dm_gradient(cfg: Config, x: np.ndarray, s: int, b: int, dms, G: np.ndarray) 
     if st != 0:
         raise ValueError(f"orc_dm_gradient failed ({st})")
     return out
+
+
+def voltage_gradient(cfg: Config, x: np.ndarray, s: int, nblock: int, dm: float,
+                     G: np.ndarray) -> np.ndarray:
+    """dL/dx for L = sum G * F at one DM over subband s and blocks 0..nblock-1
+    (G [nblock*tblk][nchan] in increasing channel frequency): complex128
+    [ntime][2], dL/dRe x = real part, dL/dIm x = imaginary part.  The adjoint
+    through the per-DM chain and the forward stage of Sec. 3, block by block,
+    overlap-added."""
+    x = _as_voltages(x)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    if G.shape != (nblock * cfg.tblk, cfg.nchan):
+        raise ValueError("G must be [nblock*tblk][nchan]")
+    xs = np.ascontiguousarray(x[s])
+    gx = np.zeros((xs.shape[0], 2, 2), dtype=np.float64)
+    for b in range(nblock):
+        gb = np.ascontiguousarray(G[b * cfg.tblk:(b + 1) * cfg.tblk])
+        st = _load().orc_voltage_gradient(ctypes.byref(cfg.c()), _kind_of(xs), xs.ctypes.data,
+                                          xs.shape[0], s, b, float(dm), gb.ctypes.data,
+                                          gx.ctypes.data)
+        if st != 0:
+            raise ValueError(f"orc_voltage_gradient failed ({st})")
+    return gx[..., 0] + 1j * gx[..., 1]
 
 
 def dedisperse(cfg: Config, x: np.ndarray, nblock: int, dms, nthreads: int = 0) -> np.ndarray:

@@ -391,6 +391,84 @@ int orc_dm_gradient(const orc_cfg *c, int kind, const void *x_sub, long ntime, i
     return 0;
 }
 
+/*
+ * Gradient of the same L with respect to the voltages of subband s, from
+ * block b and one DM: the adjoint continued through the per-DM multiply and
+ * the forward stage (Sec. 3 order reversed).  With g_S' as in
+ * orc_dm_gradient:
+ *   S'_j = spec_j h_j                        -> g_spec_j = g_S'_j conj(h_j)
+ *   spec_j = X[(j + N/2) mod N] (swap)       -> g_X[k] = g_spec[(k + N/2) mod N]
+ *   X = forward transform (e^{-}) of seg     -> g_seg = backward transform (e^{+}) of g_X
+ *   seg[n] = x[b (N - n_d n_c) + n]          -> g_x[b (N - n_d n_c) + n] += g_seg[n]
+ * gx is complex128 [ntime][2 pol] (re, im interleaved) and is ADDED to; for
+ * a real loss dL = Re sum conj(gx) dx, i.e. dL/dRe x = Re gx, dL/dIm x = Im gx.
+ */
+int orc_voltage_gradient(const orc_cfg *c, int kind, const void *x_sub, long ntime, int s, int b,
+                         double dm, const double *G, double *gx)
+{
+    if (orc_validate(c))
+        return -1;
+    const long n = c->nfft, m = n / c->nchan;
+    const long nd = c->noverlap / c->nchan;
+    const long tb = (m - nd) / c->ndec;
+    const long start = (long)b * (n - c->noverlap);
+    if (start + n > ntime)
+        return -2;
+    cplx *spec = (cplx *)malloc(sizeof(cplx) * 2 * n);
+    cplx *seg = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *z = (cplx *)malloc(sizeof(cplx) * m);
+    cplx *h = (cplx *)malloc(sizeof(cplx) * n);
+    cplx *gspec = (cplx *)malloc(sizeof(cplx) * n);
+    double *gi = (double *)malloc(sizeof(double) * m);
+    if (!spec || !seg || !z || !h || !gspec || !gi) {
+        free(spec); free(seg); free(z); free(h); free(gspec); free(gi);
+        return -3;
+    }
+    for (int p = 0; p < 2; ++p) {
+        for (long i = 0; i < n; ++i)
+            seg[i] = load_sample(kind, x_sub, start + i, p);
+        orc_fft_inplace(seg, n, -1);
+        for (long j = 0; j < n; ++j)
+            spec[p * n + j] = seg[(j + n / 2) % n];
+    }
+    for (long j = 0; j < n; ++j) {
+        double nu0, nu;
+        bin_frequency(c, s, j, n, &nu0, &nu);
+        double cyc = orc_chirp_cycles(nu, nu0, dm);
+        h[j] = cexp(I * (double)c->sign * 2.0 * ORC_PI * cyc) / (double)n;
+    }
+    for (int p = 0; p < 2; ++p) {
+        for (long ch = 0; ch < c->nchan; ++ch) {
+            for (long i = 0; i < m; ++i)
+                gi[i] = 0.0;
+            for (long t = 0; t < tb; ++t)
+                for (long q = 0; q < c->ndec; ++q)
+                    gi[nd / 2 + t * c->ndec + q] = G[t * c->nchan + ch];
+            for (long i = 0; i < m; ++i) {
+                long j = ch * m + (i + m / 2) % m;
+                z[i] = spec[p * n + j] * h[j];
+            }
+            orc_fft_inplace(z, m, +1);                      /* y */
+            for (long i = 0; i < m; ++i)
+                z[i] = 2.0 * gi[i] * z[i];                   /* g_y */
+            orc_fft_inplace(z, m, -1);                      /* g_z */
+            for (long i = 0; i < m; ++i) {
+                long j = ch * m + (i + m / 2) % m;
+                gspec[j] = z[i] * conj(h[j]);                /* g_spec */
+            }
+        }
+        for (long k = 0; k < n; ++k)
+            seg[k] = gspec[(k + n / 2) % n];                 /* g_X */
+        orc_fft_inplace(seg, n, +1);                        /* g_seg */
+        for (long i = 0; i < n; ++i) {
+            gx[((start + i) * 2 + p) * 2] += creal(seg[i]);
+            gx[((start + i) * 2 + p) * 2 + 1] += cimag(seg[i]);
+        }
+    }
+    free(spec); free(seg); free(z); free(h); free(gspec); free(gi);
+    return 0;
+}
+
 static size_t sample_bytes(int kind)
 {
     return kind == ORC_CI8 ? 4 : (kind == ORC_CF32 ? 16 : 32);

@@ -85,3 +85,50 @@ def test_gradient_is_linear_in_the_upstream_gradient():
     b = oracle.dm_gradient(cfg, x, 1, 0, dms, g2)
     c = oracle.dm_gradient(cfg, x, 1, 0, dms, 2.0 * g1 - 3.0 * g2)
     assert np.allclose(c, 2.0 * a - 3.0 * b, rtol=1e-10, atol=1e-12 * np.abs(c).max())
+
+
+def _block_loss(cfg, x, s, nblock, dm, G):
+    F = np.concatenate([oracle.subband_block(cfg, x, s, b, [dm])[0] for b in range(nblock)])
+    return float((F * G).sum())
+
+
+@pytest.mark.parametrize("mode", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
+def test_voltage_gradient_matches_exact_differences(mode):
+    """L is a quadratic form in the voltages, so central differences are exact
+    up to rounding: each perturbed component must match its gradient entry."""
+    cfg = _cfg(mode)
+    nblock = 3
+    x = synth.gaussian_voltages(cfg.nsub, cfg.ntime_in(nblock), 1.0, 31)
+    G = np.random.default_rng(6).standard_normal((nblock * cfg.tblk, cfg.nchan))
+    dm, s = 7.5, 1
+    gx = oracle.voltage_gradient(cfg, x, s, nblock, dm, G)
+    r = np.random.default_rng(7)
+    step = cfg.nfft - cfg.noverlap
+    # samples in a block's middle, in the overlap of two blocks, at both stream ends
+    ts = [5, step + 10, step + cfg.noverlap // 2, 2 * step + 100, x.shape[1] - 3,
+          int(r.integers(x.shape[1]))]
+    h = 1e-3
+    for t in ts:
+        for p in (0, 1):
+            for part, unit in ((0, 1.0), (1, 1j)):
+                xp = x.copy()
+                xm = x.copy()
+                xp[s, t, p] += h * unit
+                xm[s, t, p] -= h * unit
+                fd = (_block_loss(cfg, xp, s, nblock, dm, G) -
+                      _block_loss(cfg, xm, s, nblock, dm, G)) / (2 * h)
+                an = gx[t, p].real if part == 0 else gx[t, p].imag
+                assert abs(an - fd) <= 1e-7 * (abs(fd) + np.abs(gx).max()), (t, p, part, an, fd)
+
+
+def test_voltage_gradient_euler_identity():
+    """F is homogeneous of degree 2 in x, so sum Re(conj(dL/dx) x) = 2 L."""
+    cfg = _cfg(oracle.SUBBAND)
+    nblock = 2
+    x = synth.gaussian_voltages(cfg.nsub, cfg.ntime_in(nblock), 1.0, 32)
+    G = np.random.default_rng(9).standard_normal((nblock * cfg.tblk, cfg.nchan))
+    for s, dm in ((0, 0.0), (1, 13.0)):
+        gx = oracle.voltage_gradient(cfg, x, s, nblock, dm, G)
+        lhs = float(np.real(np.conj(gx) * x[s]).sum())
+        L = _block_loss(cfg, x, s, nblock, dm, G)
+        assert abs(lhs - 2 * L) <= 1e-9 * np.abs(G).sum() * np.abs(x[s]).max() ** 2

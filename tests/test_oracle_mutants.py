@@ -49,6 +49,14 @@ GRAD_MUTANTS = [
     ("gradient: channel swap not inverted", "long j = ch * m + (i + m / 2) % m;       /* g_S' at bin j */",
      "long j = ch * m + i;"),
     ("gradient: one polarisation", "cplx *zp = z + p * m;", "cplx *zp = z + p * m; if (p) continue;"),
+    ("voltage gradient: transfer function not conjugated", "gspec[j] = z[i] * conj(h[j]);",
+     "gspec[j] = z[i] * h[j];"),
+    ("voltage gradient: subband swap not inverted", "seg[k] = gspec[(k + n / 2) % n];",
+     "seg[k] = gspec[k];"),
+    ("voltage gradient: adjoint transform with e^-", "orc_fft_inplace(seg, n, +1);",
+     "orc_fft_inplace(seg, n, -1);"),
+    ("voltage gradient: scattered one sample late", "gx[((start + i) * 2 + p) * 2] += creal(seg[i]);",
+     "gx[((start + i + 1) * 2 + p) * 2] += creal(seg[i]);"),
 ]
 EQUIVALENT = ("no swap of halves per channel", "long j = ch * m + (i + m / 2) % m;",
               "long j = ch * m + i;")
