@@ -170,6 +170,26 @@ int cdmt_dm_gradient(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nbl
                      size_t gws_bytes, double *dldm, void *hip_stream);
 
 /*
+ * Gradient of the same kind of loss with respect to the voltages, for one DM
+ * (call once per DM with accumulate = 1 to sum over DMs): the adjoint
+ * continued through the transfer function and the forward stage (forward
+ * FFT, swap of halves, segmentation into overlapping blocks), i.e.
+ *   grad_v[s][t][p] = dL/dRe x + i dL/dIm x  (stored re, im as float32)
+ * for the voltages x that cdmt_forward turned into the spectra in workspace.
+ *   grad_out  device float32 [ntime_out][nchan_out]: dL/dF of this DM
+ *   grad_v    device float32 [nsub][ntime_in][2 pol][re, im] (layout of
+ *             complex float32 voltages); overwritten (accumulate = 0) or
+ *             added to (accumulate = 1)
+ *   gws       device, >= cdmt_voltage_gradient_workspace_size bytes
+ * FP32 arithmetic; M_bin <= 4096.  Asynchronous on hip_stream; on error
+ * nothing is written.
+ */
+int cdmt_voltage_gradient_workspace_size(cdmt_plan_t plan, int nblock, size_t *bytes);
+int cdmt_voltage_gradient(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nblock,
+                          double dm, const float *grad_out, void *gws, size_t gws_bytes,
+                          float *grad_v, int accumulate, void *hip_stream);
+
+/*
  * Redigitisation of a filterbank to 8-bit codes (Sec. 3, the paragraph after
  * the transpose; Alg. 1 "redigitize").  Independent of any plan: it takes any
  * FP32 filterbank [ndm][ntime][nchan], e.g. the output of cdmt_dedisperse.

@@ -34,7 +34,8 @@ EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
            "cdmt_redigitise_workspace_size", "cdmt_redigitise",
            "cdmt_batch_workspace_size", "cdmt_batch_create", "cdmt_batch_set", "cdmt_batch_get",
            "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy",
-           "cdmt_gradient_workspace_size", "cdmt_dm_gradient")
+           "cdmt_gradient_workspace_size", "cdmt_dm_gradient",
+           "cdmt_voltage_gradient_workspace_size", "cdmt_voltage_gradient")
 # enum cdmt_batch_opt
 CDMT_BATCH_DM_TILE, CDMT_BATCH_WG_PER_CU, CDMT_BATCH_ITEMS, CDMT_BATCH_LAUNCHES = 0, 1, 2, 3
 
@@ -90,6 +91,8 @@ def load():
         lib.cdmt_redigitise.argtypes = [P, I, LL, I, F, F, P, Z, P, P, P, P]
         lib.cdmt_gradient_workspace_size.argtypes = [P, I, I, ctypes.POINTER(Z)]
         lib.cdmt_dm_gradient.argtypes = [P, P, Z, I, ctypes.POINTER(D), I, P, P, Z, P, P]
+        lib.cdmt_voltage_gradient_workspace_size.argtypes = [P, I, ctypes.POINTER(Z)]
+        lib.cdmt_voltage_gradient.argtypes = [P, P, Z, I, D, P, P, Z, P, I, P]
         BP = ctypes.POINTER(Beam)
         lib.cdmt_batch_workspace_size.argtypes = [BP, I, ctypes.POINTER(Z)]
         lib.cdmt_batch_create.argtypes = [ctypes.POINTER(P), BP, I, P, Z]
@@ -234,6 +237,20 @@ def cdmt_dm_gradient(plan, workspace, ws_bytes, nblock, dms, grad_out, gws, gws_
                                    gws_bytes, dldm, stream), "cdmt_dm_gradient")
 
 
+def cdmt_voltage_gradient_workspace_size(plan, nblock) -> int:
+    v = ctypes.c_size_t()
+    _check(load().cdmt_voltage_gradient_workspace_size(plan, nblock, ctypes.byref(v)),
+           "cdmt_voltage_gradient_workspace_size")
+    return v.value
+
+
+def cdmt_voltage_gradient(plan, workspace, ws_bytes, nblock, dm, grad_out, gws, gws_bytes,
+                          grad_v, accumulate, stream) -> None:
+    _check(load().cdmt_voltage_gradient(plan, workspace, ws_bytes, nblock, float(dm), grad_out,
+                                        gws, gws_bytes, grad_v, int(accumulate), stream),
+           "cdmt_voltage_gradient")
+
+
 def _dm_stage_function():
     import torch
 
@@ -268,19 +285,74 @@ def _dm_stage_function():
                              ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
             return dldm.to(ctx.dms_device, ctx.dms_dtype), None, None, None
 
-    return DMStage
+    class Dedisperse(torch.autograd.Function):
+        """F = the whole path of Alg. 1 (forward stage and DM stage) for complex
+        float32 voltages x and trial DMs dms; backward gives dL/dx (through
+        cdmt_voltage_gradient, one call per DM, accumulated) and dL/dDM."""
+
+        @staticmethod
+        def forward(ctx, x, dms, plan, nblock, workspace):
+            dm_list = [float(v) for v in dms.detach().cpu().tolist()]
+            plan.forward(x.detach(), nblock, workspace)
+            _, ntout, nch = plan.shape(nblock)
+            out = torch.empty((len(dm_list), ntout, nch), dtype=torch.float32, device=x.device)
+            plan.dedisperse_spectra(nblock, dm_list, out, workspace)
+            ctx.plan, ctx.nblock, ctx.ws, ctx.dm_list = plan, nblock, workspace, dm_list
+            ctx.dms_device, ctx.dms_dtype = dms.device, dms.dtype
+            ctx.x_shape = x.shape
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            g = grad_out.detach().to(torch.float32).contiguous()
+            plan, nblock, ws = ctx.plan, ctx.nblock, ctx.ws
+            stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+            gx = gdm = None
+            if ctx.needs_input_grad[0]:
+                gx = torch.empty(ctx.x_shape, dtype=torch.float32, device=g.device)
+                gsz = cdmt_voltage_gradient_workspace_size(plan.handle, nblock)
+                gws = torch.empty(max(1, gsz), dtype=torch.uint8, device=g.device)
+                for i, dm in enumerate(ctx.dm_list):
+                    cdmt_voltage_gradient(plan.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          nblock, dm, ctypes.c_void_p(g[i].data_ptr()),
+                                          ctypes.c_void_p(gws.data_ptr()), gws.numel(),
+                                          ctypes.c_void_p(gx.data_ptr()), 1 if i else 0, stream)
+            if ctx.needs_input_grad[1]:
+                n = len(ctx.dm_list)
+                dldm = torch.empty(n, dtype=torch.float64, device=g.device)
+                gsz = cdmt_gradient_workspace_size(plan.handle, nblock, n)
+                gws = torch.empty(max(1, gsz), dtype=torch.uint8, device=g.device)
+                cdmt_dm_gradient(plan.handle, ctypes.c_void_p(ws.data_ptr()), ws.numel(), nblock,
+                                 ctx.dm_list, ctypes.c_void_p(g.data_ptr()),
+                                 ctypes.c_void_p(gws.data_ptr()), gws.numel(),
+                                 ctypes.c_void_p(dldm.data_ptr()), stream)
+                gdm = dldm.to(ctx.dms_device, ctx.dms_dtype)
+            return gx, gdm, None, None, None
+
+    return DMStage, Dedisperse
+
+
+def dedisperse(plan, x, dms, nblock, workspace):
+    """Differentiable path: filterbank of complex float32 voltages x
+    [nsub][ntime_in][2][2] at the DMs of the tensor dms; dL/dx and dL/dDM by
+    backward."""
+    global _DMStage, _Dedisperse
+    if _DMStage is None:
+        _DMStage, _Dedisperse = _dm_stage_function()
+    return _Dedisperse.apply(x, dms, plan, nblock, workspace)
 
 
 def dedisperse_dm(plan, dms, nblock, workspace):
     """Differentiable DM stage: filterbank [ndm][ntime_out][nchan_out] at the DMs
     of the tensor dms (requires_grad for dL/dDM)."""
-    global _DMStage
+    global _DMStage, _Dedisperse
     if _DMStage is None:
-        _DMStage = _dm_stage_function()
+        _DMStage, _Dedisperse = _dm_stage_function()
     return _DMStage.apply(dms, plan, nblock, workspace)
 
 
 _DMStage = None
+_Dedisperse = None
 
 
 def cdmt_batch_workspace_size(beams, nbeam) -> int:
@@ -463,4 +535,5 @@ def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
 
 __all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
                                                           "dm_seconds", "redigitise", "Batch",
-                                                          "Beam", "dedisperse_dm", "EXPORTS"]
+                                                          "Beam", "dedisperse_dm", "dedisperse",
+                                                          "EXPORTS"]

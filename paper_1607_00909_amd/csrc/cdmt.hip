@@ -951,6 +951,121 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
         part[(long long)(dm_first + d) * ncg_all + cg] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Gradient with respect to the voltages, one DM: the adjoint continued
+// through the transfer function and the forward stage.  dv_spec forms, per
+// chunk, g_spec = g_S' conj(H) as dm_grad does, and stores conj(g_spec) / N
+// with the subband's halves swapped back: the conjugated, unswapped
+// spectrum gradient.  The forward kernels then transform it as if it were a
+// stream of voltages (one block per subband-block, no overlap), which gives
+// the e^{+} transform that the adjoint needs up to conjugation, the half swap
+// and 1/N; dv_gather undoes those and overlap-adds the blocks.
+template <int M>
+__global__ __launch_bounds__(256, 2) void dv_spec(FusedArgs a, double dm,
+                                                  const float *__restrict__ gout,
+                                                  cpair *__restrict__ gin) {
+    using Sh = FusedShape<M, 16>;
+    constexpr int R = 16;
+    constexpr int T = Sh::T;
+    constexpr int C = Sh::C;
+    constexpr int STRIDE = Sh::STRIDE;
+    static_assert(Sh::WG == 256, "256-lane workgroups");
+    __shared__ cpair sh[C * STRIDE];
+
+    const int cg = a.cg0 + xcd_remap(blockIdx.x, gridDim.x);
+    const int t = threadIdx.x;
+    const int f = t / T, tt = t % T;
+    const int chunk = cg * C + f;
+    const bool valid = chunk < a.nchunks;
+    const int cc = valid ? chunk : 0;
+    const int c = cc % a.nchan;
+    const int bs = cc / a.nchan;
+    const int s = bs % a.nsub;
+    const int b = bs / a.nsub;
+
+    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
+    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
+    double nu0, off;
+    if (a.chirp_ref == 0) {
+        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
+        off = -0.5 * M;
+    } else {
+        nu0 = fs;
+        off = (double)c * M - 0.5 * a.n;
+    }
+    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
+    float2 hq[R];
+    cpair v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const double nu = ((double)(tt + T * q) + off) * a.delta;
+        const double ph = dm * (scale * nu * nu / (nu0 + nu));
+        const double n = rint(ph);
+        float sn, cs;
+        sincos_pi(static_cast<float>(ph - n), sn, cs);
+        const int flip = static_cast<int>(n) << 31;
+        hq[q] = make_float2(__int_as_float(__float_as_int(cs) ^ flip),
+                            __int_as_float(__float_as_int(sn) ^ flip));
+        const cpair r = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        v[q ^ (R / 2)] = cdmt::pmul(r, hq[q]);
+    }
+    const cdmt::LdsPad<R> lds{sh + f * STRIDE};
+    cdmt::wg_fft<M, +1>(v, tt, lds);                         // y
+
+    const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
+    const float *g = gout + (long long)b * a.tblk * a.nch_out + col;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int m = tt + T * q;
+        float gi = 0.f;
+        if (valid && m >= a.nd_half && m < M - a.nd_half)
+            gi = g[(long long)((m - a.nd_half) / a.ndec) * a.nch_out];
+        v[q] = cdmt::pscale(v[q], 2.0f * gi);
+    }
+    __syncthreads();
+    cdmt::wg_fft<M, -1>(v, tt, lds);                         // g_z
+
+    if (!valid)
+        return;
+    const float inv_n = 1.0f / (float)a.n;
+    cpair *dst = gin + (long long)bs * a.n;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const cpair gz = v[q ^ (R / 2)];                      // g_S' of bin j
+        // conj(g_S' conj(H)) / N = conj(g_S') H / N, both pols
+        const cpair cg_ = make_float4(gz.x, -gz.y, gz.z, -gz.w);
+        const cpair val = cdmt::pscale(cdmt::pmul(cg_, hq[q]), inv_n);
+        const long long j = (long long)c * M + tt + T * q;
+        dst[(j + a.n / 2) & (a.n - 1)] = val;
+    }
+}
+
+// gx[s][t] (both pols) = sum over the blocks covering sample t of
+// N conj(out[block][s][(t - start + N/2) mod N]), added to gx if accumulate
+__global__ __launch_bounds__(256) void dv_gather(const cpair *__restrict__ out, int nsub, int nfft,
+                                                 int step, int nblock, long long ntime,
+                                                 float4 *__restrict__ gx, int accumulate) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (long long)nsub * ntime)
+        return;
+    const int s = (int)(i / ntime);
+    const long long t = i - (long long)s * ntime;
+    long long blo = t - nfft + 1 <= 0 ? 0 : (t - nfft + 1 + step - 1) / step;
+    long long bhi = t / step;
+    if (bhi > nblock - 1)
+        bhi = nblock - 1;
+    float4 acc = accumulate ? gx[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+    const float fn = (float)nfft;
+    for (long long b = blo; b <= bhi; ++b) {
+        const long long n = t - b * step;
+        const cpair o = out[(b * nsub + s) * (long long)nfft + ((n + nfft / 2) & (nfft - 1))];
+        acc.x += fn * o.x;
+        acc.y -= fn * o.y;
+        acc.z += fn * o.z;
+        acc.w -= fn * o.w;
+    }
+    gx[i] = acc;
+}
+
 // dL/dDM[d] = pi * sum over chunk groups of the partials, fixed order
 __global__ __launch_bounds__(256) void dm_grad_sum(const double *__restrict__ part, long long ncg,
                                                    double *__restrict__ dldm) {
@@ -1298,6 +1413,21 @@ int launch_grad_m(const FusedArgs &a0, const double *dms, int ndm, const float *
     return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
 }
 
+template <int M>
+int launch_dv_m(const FusedArgs &a0, double dm, const float *gout, cpair *gin, long long ncg,
+                hipStream_t st) {
+    constexpr long long kMaxGroups = 0xffffffffLL / 256;
+    FusedArgs a = a0;
+    for (long long cg0 = 0; cg0 < ncg; cg0 += kMaxGroups) {
+        const long long n = ncg - cg0 < kMaxGroups ? ncg - cg0 : kMaxGroups;
+        a.cg0 = (int)cg0;
+        dv_spec<M><<<(unsigned)n, 256, 0, st>>>(a, dm, gout, gin);
+        if (hipGetLastError() != hipSuccess)
+            return CDMT_E_DEVICE;
+    }
+    return CDMT_OK;
+}
+
 long long grad_groups(const cdmt_plan_s *p, int nblock) {
     const int C = 4096 / p->m;
     return ((long long)nblock * p->nsub * p->nchan + C - 1) / C;
@@ -1573,6 +1703,73 @@ int cdmt_dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const
     case 4096: return launch_grad_m<4096>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
     default: return CDMT_E_UNSUPPORTED;
     }
+}
+
+int cdmt_voltage_gradient_workspace_size(cdmt_plan_t p, int nblock, size_t *bytes) {
+    if (!p || !bytes || nblock < 0)
+        return CDMT_E_ARG;
+    if (p->m > 4096)
+        return CDMT_E_UNSUPPORTED;
+    size_t w = 0;
+    workspace_bytes(p, nblock, &w);
+    *bytes = w / 2 * 3;                  // spectrum gradient + the forward kernels' two buffers
+    return CDMT_OK;
+}
+
+int cdmt_voltage_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, double dm,
+                          const float *grad_out, void *gws, size_t gws_bytes, float *grad_v,
+                          int accumulate, void *hip_stream) {
+    int st = check_call(p, ws, ws_bytes, nblock);
+    if (st)
+        return st;
+    if (p->m > 4096)
+        return CDMT_E_UNSUPPORTED;
+    if (accumulate != 0 && accumulate != 1)
+        return CDMT_E_ARG;
+    if (nblock == 0)
+        return CDMT_OK;
+    if (!grad_out || !gws || !grad_v)
+        return CDMT_E_ARG;
+    if (!std::isfinite(dm) || std::fabs(dm) * max_half_cycles_per_dm(p) >= 1073741824.0)
+        return CDMT_E_ARG;
+    size_t need = 0;
+    cdmt_voltage_gradient_workspace_size(p, nblock, &need);
+    if (gws_bytes < need)
+        return CDMT_E_WORKSPACE;
+    if ((st = ensure_twiddles()))
+        return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    const FusedArgs a = fused_args(p, ws, nblock, nullptr);
+    const long long ncg = grad_groups(p, nblock);
+    cpair *gin = static_cast<cpair *>(gws);
+    const long long nspec = (long long)nblock * p->nsub * p->nfft;
+    switch (p->m) {
+    case 64: st = launch_dv_m<64>(a, dm, grad_out, gin, ncg, s); break;
+    case 128: st = launch_dv_m<128>(a, dm, grad_out, gin, ncg, s); break;
+    case 256: st = launch_dv_m<256>(a, dm, grad_out, gin, ncg, s); break;
+    case 512: st = launch_dv_m<512>(a, dm, grad_out, gin, ncg, s); break;
+    case 1024: st = launch_dv_m<1024>(a, dm, grad_out, gin, ncg, s); break;
+    case 2048: st = launch_dv_m<2048>(a, dm, grad_out, gin, ncg, s); break;
+    case 4096: st = launch_dv_m<4096>(a, dm, grad_out, gin, ncg, s); break;
+    default: return CDMT_E_UNSUPPORTED;
+    }
+    if (st)
+        return st;
+    // the forward kernels on the spectrum gradient: every subband-block as
+    // one block of its own subband, float32 input, no overlap
+    cdmt_plan_s q = *p;
+    q.nsub = nblock * p->nsub;
+    q.noverlap = 0;
+    q.input_kind = 0;
+    cpair *fws = gin + nspec;
+    if ((st = launch_forward(&q, fws, gin, 1, s)))
+        return st;
+    const long long ntime = (long long)nblock * (p->nfft - p->noverlap) + p->noverlap;
+    const long long items = (long long)p->nsub * ntime;
+    dv_gather<<<(unsigned)((items + 255) / 256), 256, 0, s>>>(
+        fws, p->nsub, p->nfft, p->nfft - p->noverlap, nblock, ntime,
+        reinterpret_cast<float4 *>(grad_v), accumulate);
+    return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
 }
 
 void cdmt_destroy(cdmt_plan_t p) { delete p; }

@@ -279,3 +279,23 @@ def test_gradient_validation(lib):
     finally:
         cdmt.cdmt_destroy(p)
         cdmt.cdmt_destroy(p8)
+
+
+def test_voltage_gradient_validation(lib):
+    """cdmt_voltage_gradient argument checks, returned before any device work."""
+    import ctypes
+    p = cdmt.cdmt_plan(*GOOD)
+    try:
+        z = ctypes.c_size_t()
+        assert lib.cdmt_voltage_gradient_workspace_size(p, 2, ctypes.byref(z)) == cdmt.CDMT_OK
+        assert z.value == 3 * 2 * 8 * 16384 * 16          # three spectrum-sized buffers
+        P = ctypes.c_void_p(256)
+        big = 1 << 40
+        f = lib.cdmt_voltage_gradient
+        assert f(p, P, big, 0, 1.0, None, None, 0, None, 0, None) == cdmt.CDMT_OK       # no-op
+        assert f(p, P, big, 2, 1.0, None, P, big, P, 0, None) == cdmt.CDMT_E_ARG
+        assert f(p, P, big, 2, float("nan"), P, P, big, P, 0, None) == cdmt.CDMT_E_ARG
+        assert f(p, P, big, 2, 1.0, P, P, big, P, 2, None) == cdmt.CDMT_E_ARG           # flag
+        assert f(p, P, big, 2, 1.0, P, P, z.value - 1, P, 0, None) == cdmt.CDMT_E_WORKSPACE
+    finally:
+        cdmt.cdmt_destroy(p)

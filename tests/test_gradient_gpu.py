@@ -131,3 +131,90 @@ def test_autograd_refines_an_off_grid_dm(hip_lib):
             break
     print(f"refined DM {dm:.4f} (true {dm_true}), L {L0:.4e} -> {L:.4e}", flush=True)
     assert L > L0 and abs(dm - dm_true) < 0.02
+
+
+@pytest.mark.parametrize("mode", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
+def test_voltage_gradient_matches_oracle(hip_lib, mode):
+    """dL/dvoltage for one DM against the oracle (normwise per subband), the
+    accumulate flag, and the Euler identity sum Re(conj(dL/dx) x) = 2 L of the
+    quadratic loss, on the GPU's own forward."""
+    torch = _torch()
+    import ctypes
+    nsub, fc, nfft, nov, nchan, ndec, nblock = 3, 130.0, 8192, 2048, 8, 2, 3
+    print(f"[gpu-case] voltage gradient mode {mode}", flush=True)
+    cfg = oracle.Config(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec, chirp_ref=mode)
+    x = synth.gaussian_voltages(nsub, cfg.ntime_in(nblock), 1.0, 41)
+    v = synth.encode_cf32(x)
+    dm = 6.5
+    plan = hip_lib.Plan(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec, chirp_ref=mode,
+                        chirp_exact=1)
+    ws = plan.workspace(nblock)
+    xd = torch.from_numpy(v).cuda()
+    plan.forward(xd, nblock, ws)
+    _, ntout, nch = plan.shape(nblock)
+    G = np.random.default_rng(12).standard_normal((ntout, nch)).astype(np.float32)
+    gd = torch.from_numpy(G).cuda()
+    gsz = hip_lib.cdmt_voltage_gradient_workspace_size(plan.handle, nblock)
+    gws = torch.empty(gsz, dtype=torch.uint8, device="cuda")
+    gx = torch.full(xd.shape, float("nan"), dtype=torch.float32, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    hip_lib.cdmt_voltage_gradient(plan.handle, P(ws), ws.numel(), nblock, dm, P(gd), P(gws),
+                                  gws.numel(), P(gx), 0, None)
+    torch.cuda.synchronize()
+    got = gx.cpu().numpy().astype(np.float64)
+    got = got[..., 0] + 1j * got[..., 1]
+    worst = 0.0
+    for s in range(nsub):
+        cols = [(nsub - 1 - s) * nchan + (nchan - 1 - c) for c in range(nchan)]
+        ref = oracle.voltage_gradient(cfg, v, s, nblock, dm, G[:, cols].astype(np.float64))
+        e = np.linalg.norm(got[s] - ref) / np.linalg.norm(ref)
+        worst = max(worst, e)
+    print(f"voltage gradient vs oracle: worst normwise {worst:.2e}", flush=True)
+    assert worst <= 1e-5
+    # accumulate: a second call adds the same gradient
+    hip_lib.cdmt_voltage_gradient(plan.handle, P(ws), ws.numel(), nblock, dm, P(gd), P(gws),
+                                  gws.numel(), P(gx), 1, None)
+    torch.cuda.synchronize()
+    twice = gx.cpu().numpy().astype(np.float64)
+    both = twice[..., 0] + 1j * twice[..., 1]
+    assert np.linalg.norm(both - 2 * got) <= 1e-6 * np.linalg.norm(2 * got)
+    # Euler identity on the GPU's forward filterbank
+    F = plan.dedisperse_spectra(nblock, [dm], torch.empty((1, ntout, nch), device="cuda"), ws)
+    L = float((F[0].double() * gd.double()).sum())
+    lhs = float(np.real(np.conj(got) * (v[..., 0] + 1j * v[..., 1])).sum())
+    print(f"Euler: sum Re(conj(g) x) {lhs:.6e}, 2L {2 * L:.6e}", flush=True)
+    assert abs(lhs - 2 * L) <= 1e-5 * abs(2 * L)
+
+
+def test_autograd_voltage_and_dm_gradients(hip_lib):
+    """The autograd form returns the same gradients as the direct calls."""
+    torch = _torch()
+    import ctypes
+    print("[gpu-case] autograd voltages + DMs", flush=True)
+    nsub, fc, nfft, nov, nchan, ndec, nblock = 2, 125.0, 8192, 2048, 4, 4, 2
+    plan = hip_lib.Plan(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec, chirp_exact=1)
+    ntin, ntout, nch = plan.shape(nblock)
+    v = synth.encode_cf32(synth.gaussian_voltages(nsub, ntin, 1.0, 43))
+    ws = plan.workspace(nblock)
+    x = torch.from_numpy(v).cuda().requires_grad_(True)
+    dms = torch.tensor([2.0, 9.5, 30.0], dtype=torch.float64, requires_grad=True)
+    G = torch.randn((3, ntout, nch), device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    F = hip_lib.dedisperse(plan, x, dms, nblock, ws)
+    (F * G).sum().backward()
+    torch.cuda.synchronize()
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    gsz = hip_lib.cdmt_voltage_gradient_workspace_size(plan.handle, nblock)
+    gws = torch.empty(gsz, dtype=torch.uint8, device="cuda")
+    gx = torch.empty_like(x.detach())
+    for i, dm in enumerate(dms.tolist()):
+        hip_lib.cdmt_voltage_gradient(plan.handle, P(ws), ws.numel(), nblock, dm,
+                                      P(G[i].contiguous()), P(gws), gws.numel(), P(gx),
+                                      1 if i else 0, None)
+    n = hip_lib.cdmt_gradient_workspace_size(plan.handle, nblock, 3)
+    gws2 = torch.empty(n, dtype=torch.uint8, device="cuda")
+    dldm = torch.empty(3, dtype=torch.float64, device="cuda")
+    hip_lib.cdmt_dm_gradient(plan.handle, P(ws), ws.numel(), nblock, dms.tolist(), P(G),
+                             P(gws2), gws2.numel(), P(dldm), None)
+    torch.cuda.synchronize()
+    assert torch.equal(x.grad, gx)
+    assert torch.equal(dms.grad, dldm.cpu())
