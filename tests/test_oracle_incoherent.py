@@ -1,0 +1,120 @@
+"""Pins of the incoherent-stage oracle (semi-coherent search, Sec. 1 and
+Sec. 4): delays from Eq. 2, a dispersed spike recovered only at its DM, the
+zero-DM trial equal to the plain channel sum, and time-shift invariance."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import incoherent
+from paper_1607_00909_amd import synth
+
+
+def _cfg(mode=oracle.CHANNEL):
+    # 4 subbands at 140 MHz, 8 channels, ndec 4 -> 163.84 us samples
+    return oracle.Config(4, 140.0, synth.SUBBAND_MHZ, 16384, 4096, 8, 4, chirp_ref=mode)
+
+
+@pytest.mark.parametrize("mode", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
+def test_delays_follow_eq2(mode):
+    cfg = _cfg(mode)
+    nu = incoherent.channel_frequencies(cfg)
+    assert np.all(np.diff(nu) <= 0)                     # decreasing frequency
+    for dm in (1.0, 7.3, 40.0):
+        D = incoherent.delays(cfg, dm)
+        assert D[0] == 0 and np.all(np.diff(D) >= 0)
+        td = np.array([oracle.sweep_seconds(v, nu.max(), dm) for v in nu])
+        # whole samples within half a sample of the Eq. 2 sweep
+        assert np.all(np.abs(D - td / incoherent.sample_seconds(cfg)) <= 0.5)
+    # printed value: 163.84 us samples for 195.3125/8 kHz channels with x4 (Sec. 4 gives x1: 40.96 us)
+    assert abs(incoherent.sample_seconds(cfg) - 4 * 40.96e-6) < 1e-12
+
+
+def test_zero_dm_trial_is_the_channel_sum():
+    cfg = _cfg()
+    fb = np.random.default_rng(1).random((2, 300, cfg.nsub * cfg.nchan))
+    out = incoherent.dedisperse(cfg, fb, [0.0, 0.0], 0.0, 0.5, 3)
+    nout = out.shape[2]
+    assert np.allclose(out[:, 0], fb[:, :nout].sum(axis=2), rtol=0, atol=1e-12)
+
+
+def test_dispersed_spike_is_recovered_at_its_dm():
+    cfg = _cfg()
+    dm0 = 3.0
+    D = incoherent.delays(cfg, dm0)
+    fb = np.zeros((1, 200 + int(D.max()) + 10, cfg.nsub * cfg.nchan))
+    t0 = 120
+    fb[0, t0 + D, np.arange(fb.shape[2])] = 1.0
+    out = incoherent.dedisperse(cfg, fb, [2.5], 0.0, 0.01, 101)   # 2.5 .. 3.5
+    k0 = int(round((dm0 - 2.5) / 0.01))
+    assert out[0, k0, t0] == fb.shape[2]                # every channel aligned
+    others = np.delete(out[0, :, t0], k0)
+    # trials whose delays all round to the same samples also align; any that
+    # differ in some channel recover less
+    D_all = np.stack([incoherent.delays(cfg, 2.5 + 0.01 * k) for k in range(101)])
+    same = np.all(D_all == D, axis=1)
+    assert np.all(out[0, same, t0] == fb.shape[2])
+    assert np.all(out[0, ~same, t0] < fb.shape[2])
+    assert not np.all(same)
+
+
+def test_time_shift_invariance():
+    cfg = _cfg(oracle.SUBBAND)
+    fb = np.random.default_rng(2).random((1, 400, cfg.nsub * cfg.nchan))
+    a = incoherent.dedisperse(cfg, fb, [5.0], -0.2, 0.1, 5)
+    b = incoherent.dedisperse(cfg, fb[:, 7:], [5.0], -0.2, 0.1, 5)
+    assert np.allclose(a[:, :, 7:7 + b.shape[2]], b, rtol=0, atol=1e-12)
+
+
+def test_subband_mode_shares_a_delay_per_subband():
+    """With nu0 per subband the coherent stage aligned the channels of a
+    subband, so they share its centre's delay; per channel they differ."""
+    sub = incoherent.delays(_cfg(oracle.SUBBAND), 30.0).reshape(4, 8)
+    assert np.all(sub == sub[:, :1])
+    chan = incoherent.delays(_cfg(oracle.CHANNEL), 30.0).reshape(4, 8)
+    assert np.all(np.diff(chan, axis=1) > 0)
+
+
+def _mutant(old, new):
+    import inspect
+    import types
+    src = inspect.getsource(incoherent).replace("from . import Config, kdm",
+                                                "from oracle import Config, kdm")
+    assert old in src, old
+    m = types.ModuleType("incoherent_mutant")
+    exec(compile(src.replace(old, new, 1), "incoherent_mutant", "exec"), m.__dict__)
+    return m
+
+
+MUTANTS = {
+    "delay sign": ("u = 1.0 / (nu * nu) - 1.0 / (top * top)", "u = 1.0 / (top * top) - 1.0 / (nu * nu)"),
+    "sample time without ndec": ("return cfg.nchan * cfg.ndec / (cfg.bw * 1e6)",
+                                 "return cfg.nchan / (cfg.bw * 1e6)"),
+    "truncated delays": ("np.rint(kdm() * dm * u", "np.trunc(kdm() * dm * u"),
+    "increasing channel order": ("out[(cfg.nsub - 1 - s) * cfg.nchan + (cfg.nchan - 1 - c)] = nu",
+                                 "out[s * cfg.nchan + c] = nu"),
+    "channel centres in subband mode": ("nu = fs if cfg.chirp_ref == 1 else",
+                                        "nu = fs if cfg.chirp_ref == 7 else"),
+    "one sample short": ("fb[d, D[d, k, ch]:D[d, k, ch] + nout, ch]",
+                         "fb[d, D[d, k, ch] + 1:D[d, k, ch] + 1 + nout, ch]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_incoherent_mutants_are_caught(name, monkeypatch):
+    m = _mutant(*MUTANTS[name])
+    monkeypatch.setattr(incoherent, "channel_frequencies", m.channel_frequencies)
+    monkeypatch.setattr(incoherent, "sample_seconds", m.sample_seconds)
+    monkeypatch.setattr(incoherent, "delays", m.delays)
+    monkeypatch.setattr(incoherent, "dedisperse", m.dedisperse)
+    pins = [test_delays_follow_eq2, test_zero_dm_trial_is_the_channel_sum,
+            test_dispersed_spike_is_recovered_at_its_dm, test_time_shift_invariance,
+            test_subband_mode_shares_a_delay_per_subband]
+    caught = 0
+    for pin in pins:
+        for args in ((oracle.CHANNEL,), (oracle.SUBBAND,)) if pin is test_delays_follow_eq2 else ((),):
+            try:
+                with np.errstate(all="ignore"):
+                    pin(*args)
+            except (AssertionError, ValueError, IndexError):
+                caught += 1
+    assert caught > 0, f"mutant {name} survived every pin"
