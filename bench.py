@@ -221,6 +221,45 @@ def gradient_leg(cdmt, synth, torch, dev, steps: int):
             "gradient_dm_s_per_s": round(len(dms) * data_s / (adj / 1e3), 1)}
 
 
+def incoherent_leg(cdmt, torch, plan, w, out, dms, steps: int):
+    """The semi-coherent search's incoherent stage on the coherent output:
+    the 40 filterbanks at DM 0.5..20 (of the 128), each dedispersed
+    incoherently at 500 fine trials -0.5..+0.498 in steps of 0.002 around
+    its DM (the paper's fine grid), 20000 trials in all.  Times the whole
+    call (delay table, transpose, channel sums); the sums are bound by FP32
+    additions, one per (trial, output sample, channel)."""
+    sel = [i for i, d in enumerate(dms) if 0.5 <= d <= 20.0]
+    fb = out[sel[0]:sel[-1] + 1]
+    dm_coh = [dms[i] for i in sel]
+    ddm0, ddm, ntrial = -0.5, 0.002, 500
+    nout = cdmt.cdmt_incoherent_shape(plan.handle, w.nblock, dm_coh, ddm0, ddm, ntrial)
+    iws = torch.empty(max(1, cdmt.cdmt_incoherent_workspace_size(plan.handle, w.nblock,
+                                                                 len(dm_coh), ntrial)),
+                      dtype=torch.uint8, device=out.device)
+    iout = torch.empty((len(dm_coh), ntrial, nout), dtype=torch.float32, device=out.device)
+    stream = torch.cuda.current_stream()
+    cdmt.incoherent(plan, fb, w.nblock, dm_coh, ddm0, ddm, ntrial, out=iout, workspace=iws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        cdmt.incoherent(plan, fb, w.nblock, dm_coh, ddm0, ddm, ntrial, out=iout, workspace=iws)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    nch = fb.shape[2]
+    tsamp = w.nchan * w.ndec / (w.bw * 1e6)
+    adds = len(dm_coh) * ntrial * nout * nch
+    adds_peak = 256 * 64 * 2.4e9                 # FP32 adds per second, one per lane per clock
+    del iws, iout
+    return {"ms": round(ms, 3), "coherent_dms": len(dm_coh), "fine_trials": ntrial,
+            "nout": nout,
+            "trial_seconds_per_s": round(len(dm_coh) * ntrial * nout * tsamp / (ms / 1e3), 1),
+            "roofline": {"bound": "alu", "achieved": round(adds / (ms / 1e3) / 1e12, 2),
+                         "peak": round(adds_peak / 1e12, 2), "unit": "Tadd/s",
+                         "frac": round(adds / (ms / 1e3) / adds_peak, 4)}}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +281,8 @@ def main():
                     help="also time the 24-beam batched workload (persistent launch, hipGraph)")
     ap.add_argument("--redigitise", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the 8-bit redigitisation of the filterbank")
+    ap.add_argument("--incoherent", action=argparse.BooleanOptionalAction, default=True,
+                    help="also time the incoherent stage of a semi-coherent search")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration for profiles)")
     args = ap.parse_args()
@@ -423,6 +464,10 @@ def main():
                               "hbm_frac": round(rbytes / rms / 1e6 / HBM_PEAK_GBS, 4)}
         log(f"redigitise: {rms:.3f} ms")
         del codes, rws
+    if args.incoherent:
+        line["incoherent"] = incoherent_leg(cdmt, torch, plan, w, out, dms, args.steps)
+        log(f"incoherent: {line['incoherent']['ms']:.3f} ms")
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         threads = min(16, os.cpu_count() or 1)
         log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads")

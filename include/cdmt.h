@@ -282,6 +282,39 @@ int cdmt_batch_autotune(cdmt_batch_t batch, void *hip_stream, int reps, float *b
 /* Free a batch and its graph (NULL is accepted). */
 void cdmt_batch_destroy(cdmt_batch_t batch);
 
+/*
+ * Incoherent stage of a semi-coherent search (Sec. 1; Sec. 4, where coherent
+ * trials at coarse DM steps are followed by incoherent dedispersion at fine
+ * steps around each): for every coherent trial d the filterbank fb[d]
+ * (typically what cdmt_dedisperse wrote for dm_coh[d]) is dedispersed at the
+ * ntrial DMs  DM_dk = dm_coh[d] + (ddm0 + k ddm),  k = 0 .. ntrial-1:
+ *   out[d][k][t] = sum_ch fb[d][t + D(ch, DM_dk)][ch],   t < nout,
+ * D = the Eq. 2 delay of channel ch behind the highest channel, in output
+ * samples of nchan*ndec/bw_sub seconds, rounded half to even, computed in
+ * FP64 as  rint(((k_DM DM) u) / tsamp),  u = 1/nu^2 - 1/nu_top^2, nu the
+ * frequency the plan's chirp refers channel ch to (its centre, or its
+ * subband's centre with CDMT_CHIRP_SUBBAND); nout = ntime - the largest
+ * delay (lowest channel, largest trial DM), ntime = nblock * tblk.  Sums in
+ * FP32 over channels in increasing order.
+ *   fb         device float32 [ndm][ntime][nsub*nchan], decreasing frequency
+ *   dm_coh     host, ndm values;  every DM_dk must be >= 0
+ *   ddm        > 0 when ntrial > 1
+ *   workspace  device, >= cdmt_incoherent_workspace_size bytes (the
+ *              filterbanks transposed to [ndm][nch][ntime] and the delay
+ *              table, int32 [ndm][ntrial][nch])
+ *   out        device float32 [ndm][ntrial][nout]
+ * CDMT_E_ARG for bad DMs or steps, CDMT_E_SHAPE when nout < 1, ndm or
+ * ceil(ntrial / 16) exceeds 65535 or ntime exceeds 2^31 - 1.  Asynchronous
+ * on hip_stream; on error nothing is written.
+ */
+int cdmt_incoherent_shape(cdmt_plan_t plan, int nblock, const double *dm_coh, int ndm,
+                          double ddm0, double ddm, int ntrial, long long *nout);
+int cdmt_incoherent_workspace_size(cdmt_plan_t plan, int nblock, int ndm, int ntrial,
+                                   size_t *bytes);
+int cdmt_incoherent(cdmt_plan_t plan, int nblock, const float *fb, const double *dm_coh, int ndm,
+                    double ddm0, double ddm, int ntrial, void *workspace, size_t ws_bytes,
+                    float *out, void *hip_stream);
+
 /* Free a plan (NULL is accepted). */
 void cdmt_destroy(cdmt_plan_t plan);
 

@@ -65,3 +65,11 @@ def dedisperse(cfg: Config, fb: np.ndarray, dm_coh, ddm0: float, ddm: float, ntr
             for ch in range(fb.shape[2]):
                 out[d, k] += fb[d, D[d, k, ch]:D[d, k, ch] + nout, ch]
     return out
+
+
+def sample(cfg: Config, fb_d: np.ndarray, dm: float, ts) -> np.ndarray:
+    """Single outputs of one trial: sum_ch fb_d[t + D(ch, dm)][ch] for each t
+    in ts, fb_d one filterbank [ntime][nsub*nchan] (FP64 sums)."""
+    D = delays(cfg, dm)
+    ch = np.arange(fb_d.shape[1])
+    return np.array([np.asarray(fb_d[int(t) + D, ch], dtype=np.float64).sum() for t in ts])

@@ -35,7 +35,8 @@ EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
            "cdmt_batch_workspace_size", "cdmt_batch_create", "cdmt_batch_set", "cdmt_batch_get",
            "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy",
            "cdmt_gradient_workspace_size", "cdmt_dm_gradient",
-           "cdmt_voltage_gradient_workspace_size", "cdmt_voltage_gradient")
+           "cdmt_voltage_gradient_workspace_size", "cdmt_voltage_gradient",
+           "cdmt_incoherent_shape", "cdmt_incoherent_workspace_size", "cdmt_incoherent")
 # enum cdmt_batch_opt
 CDMT_BATCH_DM_TILE, CDMT_BATCH_WG_PER_CU, CDMT_BATCH_ITEMS, CDMT_BATCH_LAUNCHES = 0, 1, 2, 3
 
@@ -93,6 +94,10 @@ def load():
         lib.cdmt_dm_gradient.argtypes = [P, P, Z, I, ctypes.POINTER(D), I, P, P, Z, P, P]
         lib.cdmt_voltage_gradient_workspace_size.argtypes = [P, I, ctypes.POINTER(Z)]
         lib.cdmt_voltage_gradient.argtypes = [P, P, Z, I, D, P, P, Z, P, I, P]
+        lib.cdmt_incoherent_shape.argtypes = [P, I, ctypes.POINTER(D), I, D, D, I,
+                                              ctypes.POINTER(LL)]
+        lib.cdmt_incoherent_workspace_size.argtypes = [P, I, I, I, ctypes.POINTER(Z)]
+        lib.cdmt_incoherent.argtypes = [P, I, P, ctypes.POINTER(D), I, D, D, I, P, Z, P, P]
         BP = ctypes.POINTER(Beam)
         lib.cdmt_batch_workspace_size.argtypes = [BP, I, ctypes.POINTER(Z)]
         lib.cdmt_batch_create.argtypes = [ctypes.POINTER(P), BP, I, P, Z]
@@ -249,6 +254,28 @@ def cdmt_voltage_gradient(plan, workspace, ws_bytes, nblock, dm, grad_out, gws, 
     _check(load().cdmt_voltage_gradient(plan, workspace, ws_bytes, nblock, float(dm), grad_out,
                                         gws, gws_bytes, grad_v, int(accumulate), stream),
            "cdmt_voltage_gradient")
+
+
+def cdmt_incoherent_shape(plan, nblock, dm_coh, ddm0, ddm, ntrial) -> int:
+    arr, n = _dm_array(dm_coh)
+    v = ctypes.c_longlong()
+    _check(load().cdmt_incoherent_shape(plan, nblock, arr, n, float(ddm0), float(ddm), ntrial,
+                                        ctypes.byref(v)), "cdmt_incoherent_shape")
+    return v.value
+
+
+def cdmt_incoherent_workspace_size(plan, nblock, ndm, ntrial) -> int:
+    v = ctypes.c_size_t()
+    _check(load().cdmt_incoherent_workspace_size(plan, nblock, ndm, ntrial, ctypes.byref(v)),
+           "cdmt_incoherent_workspace_size")
+    return v.value
+
+
+def cdmt_incoherent(plan, nblock, fb, dm_coh, ddm0, ddm, ntrial, workspace, ws_bytes, out,
+                    stream) -> None:
+    arr, n = _dm_array(dm_coh)
+    _check(load().cdmt_incoherent(plan, nblock, fb, arr, n, float(ddm0), float(ddm), ntrial,
+                                  workspace, ws_bytes, out, stream), "cdmt_incoherent")
 
 
 def _dm_stage_function():
@@ -528,6 +555,34 @@ class Plan:
         return out
 
 
+def incoherent(plan, fb, nblock, dm_coh, ddm0, ddm, ntrial, out=None, workspace=None,
+               stream=None):
+    """Semi-coherent search's incoherent stage: the device filterbanks fb
+    [ndm][ntime][nsub*nchan] float32 (one per coherent DM in dm_coh) summed
+    over channels at the delays of DM dm_coh[d] + ddm0 + k ddm; returns
+    out [ndm][ntrial][nout] float32."""
+    import torch
+    ndm = len(dm_coh)
+    _, ntout, nch = plan.shape(nblock)
+    if (fb.dtype != torch.float32 or not fb.is_cuda or not fb.is_contiguous()
+            or tuple(fb.shape) != (ndm, ntout, nch)):
+        raise ValueError(f"fb must be a contiguous float32 device tensor {(ndm, ntout, nch)}")
+    nout = cdmt_incoherent_shape(plan.handle, nblock, dm_coh, ddm0, ddm, ntrial)
+    if out is None:
+        out = torch.empty((ndm, ntrial, nout), dtype=torch.float32, device=fb.device)
+    elif (out.dtype != torch.float32 or not out.is_contiguous()
+          or tuple(out.shape) != (ndm, ntrial, nout)):
+        raise ValueError(f"out must be a contiguous float32 tensor {(ndm, ntrial, nout)}")
+    if workspace is None:
+        workspace = torch.empty(max(1, cdmt_incoherent_workspace_size(plan.handle, nblock, ndm,
+                                                                      ntrial)),
+                                dtype=torch.uint8, device=fb.device)
+    cdmt_incoherent(plan.handle, nblock, ctypes.c_void_p(fb.data_ptr()), dm_coh, ddm0, ddm,
+                    ntrial, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                    ctypes.c_void_p(out.data_ptr()), plan._stream(stream))
+    return out
+
+
 def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
     """Seconds of data covered by nblock blocks (the metric's data-seconds)."""
     return nblock * (nfft - noverlap) / (bw_mhz * 1e6)
@@ -536,4 +591,4 @@ def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
 __all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
                                                           "dm_seconds", "redigitise", "Batch",
                                                           "Beam", "dedisperse_dm", "dedisperse",
-                                                          "EXPORTS"]
+                                                          "incoherent", "EXPORTS"]

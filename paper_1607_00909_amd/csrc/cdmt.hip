@@ -2145,3 +2145,335 @@ void cdmt_batch_destroy(cdmt_batch_t bt) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Incoherent stage of a semi-coherent search: each coherently dedispersed
+// filterbank (one per coherent DM trial) is dedispersed incoherently at fine
+// DM steps around its trial, i.e. every channel's series is shifted by its
+// dispersion delay behind the highest channel (Eq. 2, in whole output
+// samples) and the channels are summed.
+//   inc_delays     delay table D[d][ch][k] in FP64, rounded half to even; the
+//                  trial axis is padded to a multiple of kIncK with the last
+//                  trial's delay, so a workgroup reads its kIncK delays of a
+//                  channel with one scalar load
+//   inc_transpose  [d][t][ch] -> [d][ch][t] through LDS, so that the sums
+//                  read each channel's series contiguously
+//   inc_sum        one wave per (coherent DM, kIncK fine trials, kIncT output
+//                  samples), each lane owning kIncS consecutive samples.  Per
+//                  channel the wave stages the window its trials read (the
+//                  tile plus the spread of their delays) in LDS once; the
+//                  delays grow with the trial index, so a lane re-reads its
+//                  kIncS values only when the delay changes and otherwise
+//                  adds the ones it holds.  Windows wider than the LDS buffer
+//                  (very coarse steps) read global memory per trial instead.
+
+namespace {
+
+struct IncArgs {
+    int nsub, nchan, nch, ntrial, kpad, chirp_ref;
+    long long ntime, nout;
+    double f_centre, bw, tsamp, ddm0, ddm;
+};
+
+constexpr int kIncS = 4;                      // consecutive samples per lane
+constexpr int kIncT = 64 * kIncS;             // output samples per workgroup
+constexpr int kIncK = 16;                     // fine trials per workgroup
+constexpr int kIncSpan = 256;                 // widest delay spread staged in LDS
+
+// (both functions evaluate exactly as written, with no fused multiply-adds,
+// so that every rounding of a delay to whole samples is reproducible)
+__host__ __device__ inline double inc_frequency(const IncArgs &a, int ch) {
+#pragma clang fp contract(off)
+    const int s = a.nsub - 1 - ch / a.nchan;
+    const int c = a.nchan - 1 - ch % a.nchan;
+    const double fs = a.f_centre + ((double)s - (a.nsub - 1) / 2.0) * a.bw;
+    return a.chirp_ref == 1 ? fs : fs - a.bw / 2.0 + (c + 0.5) * a.bw / a.nchan;
+}
+
+__host__ __device__ inline long long inc_delay(const IncArgs &a, double dm, int ch) {
+#pragma clang fp contract(off)
+    const double nu = inc_frequency(a, ch);
+    const double top = inc_frequency(a, 0);
+    const double u = 1.0 / (nu * nu) - 1.0 / (top * top);
+    return (long long)rint(kKdm * dm * u / a.tsamp);
+}
+
+__global__ __launch_bounds__(256) void inc_delays(IncArgs a, DmList dl, int first, int cnt,
+                                                  int *__restrict__ D) {
+#pragma clang fp contract(off)
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long per = (long long)a.nch * a.kpad;
+    if (i >= per * cnt)
+        return;
+    const int dl_i = (int)(i / per);
+    const int ch = (int)((i % per) / a.kpad);
+    const int k = min((int)(i % a.kpad), a.ntrial - 1);
+    const double dm = dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)k);
+    D[(long long)(first + dl_i) * per + (i % per)] = (int)inc_delay(a, dm, ch);
+}
+
+__global__ __launch_bounds__(256) void inc_transpose(const float *__restrict__ fb,
+                                                     float *__restrict__ ft, long long ntime,
+                                                     int nch) {
+    __shared__ float tile[32][33];
+    const long long t0 = (long long)blockIdx.x * 32;
+    const int c0 = blockIdx.y * 32;
+    const long long d = blockIdx.z;
+    const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;     // 32 x 8
+    for (int r = ty; r < 32; r += 8) {
+        const long long t = t0 + r;
+        const int ch = c0 + tx;
+        tile[r][tx] = (t < ntime && ch < nch) ? fb[(d * ntime + t) * nch + ch] : 0.f;
+    }
+    __syncthreads();
+    for (int r = ty; r < 32; r += 8) {
+        const int ch = c0 + r;
+        const long long t = t0 + tx;
+        if (ch < nch && t < ntime)
+            ft[(d * nch + ch) * ntime + t] = tile[tx][r];
+    }
+}
+
+// Adds v to a without letting the compiler move the addition: each trial's
+// sums then follow the window load they use, and the window registers are not
+// duplicated to serve additions deferred past the next reload.
+__device__ __forceinline__ void inc_add(float &a, float v) {
+    asm volatile("v_add_f32 %0, %1, %0" : "+v"(a) : "v"(v));
+}
+
+// WIDE = false: every trial group's delay spread in every channel is below
+// kIncSpan (the host proves it from the lowest channel's delay per DM), so
+// the window fits the LDS buffer; WIDE = true reads global memory per trial.
+template <bool WIDE>
+__global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
+                                              const int *__restrict__ D, IncArgs a, int ntile,
+                                              int ngroup, float *__restrict__ out) {
+    constexpr int kPf = kIncT / 64 + 1;             // window loads per lane for spreads < 64
+    __shared__ float win[WIDE ? 1 : kIncT + kIncSpan];
+    // XCD-aware order: the trial groups of one time tile run on one XCD
+    // together and share its L2 copy of the tile's windows
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int kgi = lw % ngroup;
+    const int tile = (lw / ngroup) % ntile;
+    const long long d = lw / (ngroup * ntile);
+    const int kg = kgi * kIncK;
+    const long long t0 = (long long)tile * kIncT;
+    const int lane = threadIdx.x;
+    float acc[kIncK][kIncS];
+#pragma unroll
+    for (int k = 0; k < kIncK; ++k)
+#pragma unroll
+        for (int j = 0; j < kIncS; ++j)
+            acc[k][j] = 0.f;
+    const float *base = ft + d * a.nch * a.ntime + t0;
+    const int *Dd = D + d * a.nch * a.kpad + kg;
+    const int room = (int)(a.ntime - 1 - t0);       // last readable offset from t0
+    if constexpr (WIDE) {
+        for (int ch = 0; ch < a.nch; ++ch) {
+            const int *dk = Dd + (long long)ch * a.kpad;
+            const int lo = dk[0];
+            const float *row = base + (long long)ch * a.ntime + lo;
+            const int last = room - lo;
+#pragma unroll
+            for (int k = 0; k < kIncK; ++k) {
+                const int o = dk[k] - lo;
+#pragma unroll
+                for (int j = 0; j < kIncS; ++j)
+                    acc[k][j] += row[min(kIncS * lane + o + j, last)];
+            }
+        }
+    } else {
+        // the next channel's delays and window are loaded while the current
+        // channel's trials are summed
+        int offn[kIncK];
+        float pf[kPf];
+#pragma unroll
+        for (int k = 0; k < kIncK; ++k)
+            offn[k] = Dd[k];
+        {
+            const int last = room - offn[0];
+#pragma unroll
+            for (int m = 0; m < kPf; ++m)
+                pf[m] = base[offn[0] + min(lane + 64 * m, last)];
+        }
+        for (int ch = 0; ch < a.nch; ++ch) {
+            int off[kIncK];
+#pragma unroll
+            for (int k = 0; k < kIncK; ++k)
+                off[k] = offn[k];
+            const int lo = off[0];
+            // (the clamp only keeps LDS indexes in range; the host has shown
+            // that the spread is below kIncSpan)
+            const int span = min(off[kIncK - 1] - lo, kIncSpan - 1);
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < kPf; ++m)
+                win[lane + 64 * m] = pf[m];
+            if (span >= 64 * kPf - kIncT) {             // rare: wide spread, load the rest now
+                const float *row = base + (long long)ch * a.ntime + lo;
+                const int last = room - lo;
+#pragma unroll 1
+                for (int m = kPf; 64 * m < kIncT + span; ++m)
+                    win[lane + 64 * m] = row[min(lane + 64 * m, last)];
+            }
+            if (ch + 1 < a.nch) {
+#pragma unroll
+                for (int k = 0; k < kIncK; ++k)
+                    offn[k] = Dd[(long long)(ch + 1) * a.kpad + k];
+                const float *row = base + (long long)(ch + 1) * a.ntime + offn[0];
+                const int last = room - offn[0];
+#pragma unroll
+                for (int m = 0; m < kPf; ++m)
+                    pf[m] = row[min(lane + 64 * m, last)];
+            }
+            __syncthreads();
+            int held = -1;
+            float w[kIncS];
+#pragma unroll
+            for (int k = 0; k < kIncK; ++k) {
+                const int o = min(off[k] - lo, span);
+                if (o != held) {
+                    held = o;
+#pragma unroll
+                    for (int j = 0; j < kIncS; ++j)
+                        w[j] = win[kIncS * lane + o + j];
+                }
+#pragma unroll
+                for (int j = 0; j < kIncS; ++j)
+                    inc_add(acc[k][j], w[j]);
+            }
+        }
+    }
+    const int nk = min(kIncK, a.ntrial - kg);
+#pragma unroll
+    for (int k = 0; k < kIncK; ++k) {
+        if (k < nk) {
+            float *o = out + (d * a.ntrial + kg + k) * a.nout + t0 + kIncS * lane;
+#pragma unroll
+            for (int j = 0; j < kIncS; ++j)
+                if (t0 + kIncS * lane + j < a.nout)
+                    o[j] = acc[k][j];
+        }
+    }
+}
+
+// Bound on the delay spread of kIncK consecutive trials in any channel: the
+// delay rint(c DM) of channel ch has c = k_DM u / tsamp, largest in the lowest
+// channel, so the spread is at most c_max (kIncK - 1) ddm + 1.
+bool inc_narrow(const IncArgs &a) {
+    const double nu = inc_frequency(a, a.nch - 1), top = inc_frequency(a, 0);
+    const double cmax = kKdm * (1.0 / (nu * nu) - 1.0 / (top * top)) / a.tsamp;
+    return cmax * (kIncK - 1) * a.ddm * (1.0 + 1e-9) + 2.0 < (double)kIncSpan;
+}
+
+int inc_setup(const cdmt_plan_s *p, int nblock, const double *dm_coh, int ndm, double ddm0,
+              double ddm, int ntrial, IncArgs *a) {
+    if (!p || nblock < 1 || ndm < 1 || !dm_coh || ntrial < 1 || !std::isfinite(ddm0) ||
+        !std::isfinite(ddm) || (ntrial > 1 && !(ddm > 0.0)))
+        return CDMT_E_ARG;
+    std::memset(a, 0, sizeof(*a));
+    a->nsub = p->nsub;
+    a->nchan = p->nchan;
+    a->nch = p->nsub * p->nchan;
+    a->ntrial = ntrial;
+    a->kpad = (ntrial + kIncK - 1) / kIncK * kIncK;
+    a->chirp_ref = p->chirp_ref;
+    a->ntime = (long long)nblock * p->tblk;
+    a->f_centre = p->f_centre;
+    a->bw = p->bw;
+    a->tsamp = (double)(p->nchan * p->ndec) / (p->bw * 1e6);
+    a->ddm0 = ddm0;
+    a->ddm = ddm;
+    // every trial DM non-negative (delays behind the top channel); the delay
+    // grows with DM and is largest in the lowest channel
+    double dmax = -1.0;
+    for (int d = 0; d < ndm; ++d) {
+        if (!std::isfinite(dm_coh[d]) || dm_coh[d] + (ddm0 + ddm * 0.0) < 0.0)
+            return CDMT_E_ARG;
+        dmax = std::fmax(dmax, dm_coh[d] + (ddm0 + ddm * (double)(ntrial - 1)));
+    }
+    if (a->ntime > 0x7fffffffLL)
+        return CDMT_E_SHAPE;
+    const long long dl = inc_delay(*a, dmax, a->nch - 1);
+    a->nout = a->ntime - dl;
+    if (a->nout < 1)
+        return CDMT_E_SHAPE;
+    // one workgroup per (DM, time tile, trial group) in a 1-D grid
+    const long long groups = (long long)ndm * ((a->nout + kIncT - 1) / kIncT) * (a->kpad / kIncK);
+    return groups <= 0x7fffffffLL ? CDMT_OK : CDMT_E_SHAPE;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cdmt_incoherent_shape(cdmt_plan_t p, int nblock, const double *dm_coh, int ndm, double ddm0,
+                          double ddm, int ntrial, long long *nout) {
+    if (!nout)
+        return CDMT_E_ARG;
+    IncArgs a;
+    const int st = inc_setup(p, nblock, dm_coh, ndm, ddm0, ddm, ntrial, &a);
+    if (st)
+        return st;
+    *nout = a.nout;
+    return CDMT_OK;
+}
+
+int cdmt_incoherent_workspace_size(cdmt_plan_t p, int nblock, int ndm, int ntrial, size_t *bytes) {
+    if (!p || !bytes || nblock < 0 || ndm < 0 || ntrial < 0)
+        return CDMT_E_ARG;
+    const size_t nch = (size_t)p->nsub * p->nchan;
+    const size_t ntime = (size_t)nblock * p->tblk;
+    const size_t ft = (size_t)ndm * nch * ntime * sizeof(float);
+    const size_t kpad = ((size_t)ntrial + kIncK - 1) / kIncK * kIncK;
+    *bytes = ((ft + 255) & ~(size_t)255) + (size_t)ndm * kpad * nch * sizeof(int);
+    return CDMT_OK;
+}
+
+int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm_coh, int ndm,
+                    double ddm0, double ddm, int ntrial, void *ws, size_t ws_bytes, float *out,
+                    void *hip_stream) {
+    IncArgs a;
+    int st = inc_setup(p, nblock, dm_coh, ndm, ddm0, ddm, ntrial, &a);
+    if (st)
+        return st;
+    if (!fb || !ws || !out)
+        return CDMT_E_ARG;
+    size_t need = 0;
+    cdmt_incoherent_workspace_size(p, nblock, ndm, ntrial, &need);
+    if (ws_bytes < need)
+        return CDMT_E_WORKSPACE;
+    const long long tiles_t = (a.ntime + 31) / 32;
+    const long long ndelay = ((long long)std::min(ndm, kMaxDmPerLaunch) * a.kpad * a.nch + 255) / 256;
+    if ((a.nch + 31) / 32 > 65535 || ndm > 65535 || ndelay > 0x7fffffffLL)
+        return CDMT_E_SHAPE;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    float *ft = static_cast<float *>(ws);
+    const size_t ftb = (size_t)ndm * a.nch * a.ntime * sizeof(float);
+    int *D = reinterpret_cast<int *>(static_cast<char *>(ws) + ((ftb + 255) & ~(size_t)255));
+    for (int first = 0; first < ndm; first += kMaxDmPerLaunch) {
+        const int cnt = ndm - first < kMaxDmPerLaunch ? ndm - first : kMaxDmPerLaunch;
+        DmList dl;
+        std::memset(&dl, 0, sizeof(dl));
+        for (int i = 0; i < cnt; ++i)
+            dl.dm[i] = dm_coh[first + i];
+        const long long n = (long long)cnt * a.kpad * a.nch;
+        inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt, D);
+        if (hipGetLastError() != hipSuccess)
+            return CDMT_E_DEVICE;
+    }
+    inc_transpose<<<dim3((unsigned)tiles_t, (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256, 0,
+                    s>>>(fb, ft, a.ntime, a.nch);
+    if (hipGetLastError() != hipSuccess)
+        return CDMT_E_DEVICE;
+    const int ntile = (int)((a.nout + kIncT - 1) / kIncT);
+    const int ngroup = a.kpad / kIncK;
+    const unsigned grid = (unsigned)((long long)ndm * ntile * ngroup);
+    if (a.ntrial == 1 || inc_narrow(a))
+        inc_sum<false><<<grid, 64, 0, s>>>(ft, D, a, ntile, ngroup, out);
+    else
+        inc_sum<true><<<grid, 64, 0, s>>>(ft, D, a, ntile, ngroup, out);
+    return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
+}
+
+}  // extern "C"

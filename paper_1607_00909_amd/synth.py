@@ -201,3 +201,30 @@ def device_noise(kind: str, nsub: int, ntime: int, sigma: float, seed: int, devi
             out[s0:s1] = z
         del z
     return out
+
+
+def filterbank(ndm: int, ntime: int, nch: int, seed: int, kind: str = "power") -> np.ndarray:
+    """Synthetic detected filterbanks [ndm][ntime][nch] float32: "power" is
+    what detection of complex Gaussian noise in two polarisations gives (a
+    sum of four squared unit normals, chi-square with 4 degrees of freedom);
+    "codes" are integers 0..255 (exactly representable, so sums of a few
+    thousand of them are exact in float32)."""
+    g = np.random.default_rng(np.random.SeedSequence([seed, 424242]))
+    if kind == "codes":
+        return g.integers(0, 256, size=(ndm, ntime, nch)).astype(np.float32)
+    z = g.standard_normal((ndm, ntime, nch, 4))
+    return (z * z).sum(axis=3).astype(np.float32)
+
+
+def device_filterbank(ndm: int, ntime: int, nch: int, seed: int, device):
+    """The "power" filterbank of the same distribution generated in device
+    memory with torch's seeded generator (for sizes too big for the host)."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    out = torch.empty((ndm, ntime, nch), dtype=torch.float32, device=device)
+    for d in range(ndm):
+        z = torch.randn((ntime, nch, 4), generator=gen, device=device, dtype=torch.float32)
+        out[d] = (z * z).sum(dim=2)
+        del z
+    return out

@@ -299,3 +299,40 @@ def test_voltage_gradient_validation(lib):
         assert f(p, P, big, 2, 1.0, P, P, z.value - 1, P, 0, None) == cdmt.CDMT_E_WORKSPACE
     finally:
         cdmt.cdmt_destroy(p)
+
+
+def test_incoherent_validation(lib):
+    """cdmt_incoherent_shape agrees with the oracle's output length (the
+    largest Eq. 2 delay), and the argument checks return before device work."""
+    import ctypes
+    from oracle import incoherent
+    p = cdmt.cdmt_plan(*GOOD)
+    try:
+        cfg = oracle.Config(*GOOD)
+        tblk = (16384 // 8 - 4096 // 8) // 4
+        for dms, ddm0, ddm, n in (([0.5, 10.0, 20.0], -0.5, 0.01, 101), ([3.0], 0.0, 0.0, 1),
+                                  ([1.0, 2.0], 0.0, 2.0, 10)):
+            nout = cdmt.cdmt_incoherent_shape(p, 4, dms, ddm0, ddm, n)
+            dmax = max(dms) + (ddm0 + ddm * (n - 1))
+            assert nout == 4 * tblk - int(incoherent.delays(cfg, dmax).max())
+        z = ctypes.c_size_t()
+        assert lib.cdmt_incoherent_workspace_size(p, 4, 3, 101, ctypes.byref(z)) == cdmt.CDMT_OK
+        assert z.value == 3 * 64 * 4 * tblk * 4 + 3 * 112 * 64 * 4   # transposed copy, delays
+        arr = (ctypes.c_double * 3)(0.5, 10.0, 20.0)
+        nout = ctypes.c_longlong()
+        shape = lib.cdmt_incoherent_shape
+        assert shape(p, 4, arr, 3, -0.5, 0.01, 101, ctypes.byref(nout)) == cdmt.CDMT_OK
+        assert shape(p, 4, arr, 3, -0.6, 0.01, 101, ctypes.byref(nout)) == cdmt.CDMT_E_ARG  # DM < 0
+        assert shape(p, 4, arr, 3, 0.0, 0.0, 2, ctypes.byref(nout)) == cdmt.CDMT_E_ARG      # step
+        assert shape(p, 4, arr, 3, 0.0, -0.1, 2, ctypes.byref(nout)) == cdmt.CDMT_E_ARG
+        assert shape(p, 4, arr, 3, float("nan"), 0.1, 2, ctypes.byref(nout)) == cdmt.CDMT_E_ARG
+        assert shape(p, 4, arr, 0, 0.0, 0.1, 2, ctypes.byref(nout)) == cdmt.CDMT_E_ARG
+        assert shape(p, 4, arr, 3, 0.0, 0.1, 0, ctypes.byref(nout)) == cdmt.CDMT_E_ARG
+        assert shape(p, 1, arr, 3, 0.0, 1.0, 900, ctypes.byref(nout)) == cdmt.CDMT_E_SHAPE  # no sample
+        P = ctypes.c_void_p(256)
+        f = lib.cdmt_incoherent
+        assert f(p, 4, P, arr, 3, -0.5, 0.01, 101, P, z.value - 1, P, None) == cdmt.CDMT_E_WORKSPACE
+        assert f(p, 4, None, arr, 3, -0.5, 0.01, 101, P, z.value, P, None) == cdmt.CDMT_E_ARG
+        assert f(p, 4, P, arr, 3, -0.5, 0.01, 101, P, z.value, None, None) == cdmt.CDMT_E_ARG
+    finally:
+        cdmt.cdmt_destroy(p)

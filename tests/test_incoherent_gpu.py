@@ -1,0 +1,120 @@
+"""GPU incoherent stage (cdmt_incoherent) against the oracle's incoherent
+dedispersion (Eq. 2 delays, channel sums).
+
+Bars: with integer-valued filterbanks every FP32 sum is exact, so the GPU
+must equal the oracle exactly, which pins every delay.  With real-valued
+power the GPU sums nch float32 terms in order, so |gpu - exact| <=
+gamma_(nch-1) * sum_ch |x| with gamma_n = n u / (1 - n u), u = 2^-24."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import incoherent
+from paper_1607_00909_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _gamma(n):
+    u = 2.0 ** -24
+    return n * u / (1 - n * u)
+
+
+def _run(hip_lib, cfg, nblock, fb, dms, ddm0, ddm, ntrial):
+    torch = _torch()
+    plan = hip_lib.Plan(cfg.nsub, cfg.f_centre, cfg.bw, cfg.nfft, cfg.noverlap, cfg.nchan,
+                        cfg.ndec, chirp_ref=cfg.chirp_ref)
+    out = hip_lib.incoherent(plan, torch.from_numpy(fb).cuda(), nblock, dms, ddm0, ddm, ntrial)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+CASES = {
+    # name: (chirp reference, dms, ddm0, ddm, ntrial)
+    "channel-fine": (oracle.CHANNEL, [0.5, 3.0, 7.0], -0.5, 0.01, 101),
+    "subband-fine": (oracle.SUBBAND, [1.0, 6.0], -0.25, 0.005, 37),
+    "one-trial-dm0": (oracle.CHANNEL, [0.5, 2.0], -0.5, 0.0, 1),
+    "spread-over-64": (oracle.CHANNEL, [0.0, 1.0], 0.0, 0.5, 16),
+    "coarse-global": (oracle.CHANNEL, [1.0, 2.0], 0.0, 2.0, 10),
+}
+
+
+@pytest.mark.parametrize("kind", ["codes", "power"])
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_incoherent_parity(hip_lib, name, kind):
+    mode, dms, ddm0, ddm, ntrial = CASES[name]
+    # 4 subbands at 140 MHz, 8 channels each, 163.84 us samples; 4 blocks of
+    # 384 samples: several 256-sample tiles and a ragged tail
+    cfg = oracle.Config(4, 140.0, synth.SUBBAND_MHZ, 16384, 4096, 8, 4, chirp_ref=mode)
+    nblock = 4
+    ntime = nblock * cfg.tblk
+    nch = cfg.nsub * cfg.nchan
+    print(f"[gpu-case] incoherent {name} {kind}", flush=True)
+    fb = synth.filterbank(len(dms), ntime, nch, 90 + len(name), kind)
+    gpu = _run(hip_lib, cfg, nblock, fb, dms, ddm0, ddm, ntrial)
+    ref = incoherent.dedisperse(cfg, fb, dms, ddm0, ddm, ntrial)
+    assert gpu.shape == ref.shape
+    if kind == "codes":
+        assert np.array_equal(gpu.astype(np.float64), ref)
+    else:
+        bound = _gamma(nch - 1) * ref                # positive terms: sum |x| = the sum
+        err = np.abs(gpu.astype(np.float64) - ref)
+        print(f"{name}: max err / bound {np.max(err / bound):.3f}", flush=True)
+        assert np.all(err <= bound)
+
+
+def test_incoherent_recovers_a_dispersed_spike(hip_lib):
+    """A spike dispersed at DM 3 (one sample per channel on the Eq. 2 sweep)
+    adds up in every channel only at trials whose delays all match DM 3's."""
+    cfg = oracle.Config(4, 140.0, synth.SUBBAND_MHZ, 16384, 4096, 8, 4)
+    nblock = 2
+    nch = cfg.nsub * cfg.nchan
+    D = incoherent.delays(cfg, 3.0)
+    fb = np.zeros((1, nblock * cfg.tblk, nch), np.float32)
+    t0 = 300
+    fb[0, t0 + D, np.arange(nch)] = 1.0
+    gpu = _run(hip_lib, cfg, nblock, fb, [3.0], -0.5, 0.01, 101)
+    D_all = np.stack([incoherent.delays(cfg, 2.5 + 0.01 * k) for k in range(101)])
+    same = np.all(D_all == D, axis=1)
+    assert same[50] and not np.all(same)
+    assert np.all(gpu[0, same, t0] == nch)
+    assert np.all(gpu[0, ~same, t0] < nch)
+
+
+def test_incoherent_lofar_scale_samples(hip_lib):
+    """At full size: 288 subbands x 16 channels, 39 blocks (15288 samples of
+    655.36 us), coherent DMs 0.5..20 and 500 fine trials -0.5..+0.498 in
+    steps of 0.002 around each; sampled outputs against the oracle's sums."""
+    torch = _torch()
+    w = synth.LOFAR
+    cfg = oracle.Config(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+    plan = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+    dms = [0.5 * (i + 1) for i in range(40)]
+    print("[gpu-case] incoherent lofar-scale", flush=True)
+    _, ntout, nch = plan.shape(w.nblock)
+    fb = synth.device_filterbank(len(dms), ntout, nch, 2024, "cuda")
+    out = hip_lib.incoherent(plan, fb, w.nblock, dms, -0.5, 0.002, 500)
+    torch.cuda.synchronize()
+    nout = out.shape[2]
+    assert nout == ntout - int(incoherent.delays(cfg, 20.0 + (-0.5 + 0.002 * 499)).max())
+    r = np.random.default_rng(5)
+    worst = 0.0
+    for d in (0, 17, 39):
+        fb_d = fb[d].cpu().numpy()
+        ks = list(r.integers(0, 500, 6)) + [0, 499]
+        for k in ks:
+            ts = list(r.integers(0, nout, 5)) + [0, nout - 1]
+            dm = dms[d] + (-0.5 + 0.002 * int(k))
+            ref = incoherent.sample(cfg, fb_d, dm, ts)
+            got = out[d, int(k), ts].cpu().numpy().astype(np.float64)
+            err = np.abs(got - ref) / (_gamma(nch - 1) * ref)
+            worst = max(worst, float(err.max()))
+    print(f"lofar-scale: max err / bound {worst:.3f}", flush=True)
+    assert worst <= 1.0
