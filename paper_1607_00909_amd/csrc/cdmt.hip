@@ -2152,10 +2152,12 @@ void cdmt_batch_destroy(cdmt_batch_t bt) {
 // DM steps around its trial, i.e. every channel's series is shifted by its
 // dispersion delay behind the highest channel (Eq. 2, in whole output
 // samples) and the channels are summed.
-//   inc_delays     delay table D[d][ch][k] in FP64, rounded half to even; the
-//                  trial axis is padded to a multiple of kIncK with the last
-//                  trial's delay, so a workgroup reads its kIncK delays of a
-//                  channel with one scalar load
+//   inc_delays     delay table in FP64, rounded half to even, laid out
+//                  [d][ch][k] with the trial axis padded to a multiple of kIncK
+//                  (padding repeats the last trial): per group of kIncK trials
+//                  the first entry is the group's first delay and the others
+//                  are relative to it, so a workgroup reads what it needs for
+//                  a channel with one scalar load
 //   inc_transpose  [d][t][ch] -> [d][ch][t] through LDS, so that the sums
 //                  read each channel's series contiguously
 //   inc_sum        one wave per (coherent DM, kIncK fine trials, kIncT output
@@ -2199,7 +2201,7 @@ __host__ __device__ inline long long inc_delay(const IncArgs &a, double dm, int 
 }
 
 __global__ __launch_bounds__(256) void inc_delays(IncArgs a, DmList dl, int first, int cnt,
-                                                  int *__restrict__ D) {
+                                                  int clamp, int *__restrict__ D) {
 #pragma clang fp contract(off)
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const long long per = (long long)a.nch * a.kpad;
@@ -2207,9 +2209,14 @@ __global__ __launch_bounds__(256) void inc_delays(IncArgs a, DmList dl, int firs
         return;
     const int dl_i = (int)(i / per);
     const int ch = (int)((i % per) / a.kpad);
-    const int k = min((int)(i % a.kpad), a.ntrial - 1);
+    const int kr = (int)(i % a.kpad);
+    const int k0 = kr - kr % kIncK;                // first trial of the group (< ntrial)
+    const int k = min(kr, a.ntrial - 1);
+    const double dm0 = dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)k0);
     const double dm = dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)k);
-    D[(long long)(first + dl_i) * per + (i % per)] = (int)inc_delay(a, dm, ch);
+    const int lo = (int)inc_delay(a, dm0, ch);
+    const int v = kr == k0 ? lo : min((int)inc_delay(a, dm, ch) - lo, clamp);
+    D[(long long)(first + dl_i) * per + (i % per)] = v;
 }
 
 __global__ __launch_bounds__(256) void inc_transpose(const float *__restrict__ fb,
@@ -2241,6 +2248,16 @@ __device__ __forceinline__ void inc_add(float &a, float v) {
     asm volatile("v_add_f32 %0, %1, %0" : "+v"(a) : "v"(v));
 }
 
+// Raw buffer view of the n floats at p: loads at byte offsets >= 4n read 0
+// (the hardware range check), which replaces clamping of window indexes.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t inc_view(const float *p, int n) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(p), (short)0, 4 * n, 0x00020000);
+}
+
+__device__ __forceinline__ float inc_load(__amdgpu_buffer_rsrc_t v, int byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v, byte_off, 0, 0));
+}
+
 // WIDE = false: every trial group's delay spread in every channel is below
 // kIncSpan (the host proves it from the lowest channel's delay per DM), so
 // the window fits the LDS buffer; WIDE = true reads global memory per trial.
@@ -2265,74 +2282,73 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
 #pragma unroll
         for (int j = 0; j < kIncS; ++j)
             acc[k][j] = 0.f;
-    const float *base = ft + d * a.nch * a.ntime + t0;
-    const int *Dd = D + d * a.nch * a.kpad + kg;
-    const int room = (int)(a.ntime - 1 - t0);       // last readable offset from t0
+    // delays of channel ch: dk[0] = first trial's, dk[k] = trial k's minus it
+    const int *dk = D + d * a.nch * a.kpad + kg;
+    const float *row = ft + d * a.nch * a.ntime + t0;      // channel ch's series at t0
+    const int room = (int)(a.ntime - 1 - t0);           // last readable offset from row
     if constexpr (WIDE) {
-        for (int ch = 0; ch < a.nch; ++ch) {
-            const int *dk = Dd + (long long)ch * a.kpad;
+        for (int ch = 0; ch < a.nch; ++ch, dk += a.kpad, row += a.ntime) {
             const int lo = dk[0];
-            const float *row = base + (long long)ch * a.ntime + lo;
             const int last = room - lo;
 #pragma unroll
             for (int k = 0; k < kIncK; ++k) {
-                const int o = dk[k] - lo;
+                const int o = k == 0 ? 0 : dk[k];
 #pragma unroll
                 for (int j = 0; j < kIncS; ++j)
-                    acc[k][j] += row[min(kIncS * lane + o + j, last)];
+                    acc[k][j] += row[lo + min(kIncS * lane + o + j, last)];
             }
         }
     } else {
-        // the next channel's delays and window are loaded while the current
-        // channel's trials are summed
-        int offn[kIncK];
+        // The next channel's delays and window are loaded while the current
+        // channel's trials are summed; the delays alternate between two
+        // arrays (channel pairs) so that none are copied.  view(lo) covers
+        // the kIncT + kIncSpan samples from a channel's first delay on (fewer
+        // at the end of the series).
+        const auto view = [&](int lo) {
+            return inc_view(row + lo, min(room - lo + 1, kIncT + kIncSpan));
+        };
+        int offa[kIncK], offb[kIncK];
         float pf[kPf];
 #pragma unroll
         for (int k = 0; k < kIncK; ++k)
-            offn[k] = Dd[k];
+            offa[k] = dk[k];
         {
-            const int last = room - offn[0];
+            const auto v = view(offa[0]);
 #pragma unroll
             for (int m = 0; m < kPf; ++m)
-                pf[m] = base[offn[0] + min(lane + 64 * m, last)];
+                pf[m] = inc_load(v, 4 * (lane + 64 * m));
         }
-        for (int ch = 0; ch < a.nch; ++ch) {
-            int off[kIncK];
-#pragma unroll
-            for (int k = 0; k < kIncK; ++k)
-                off[k] = offn[k];
+        const auto step = [&](int ch, const int (&off)[kIncK], int (&offn)[kIncK]) {
             const int lo = off[0];
-            // (the clamp only keeps LDS indexes in range; the host has shown
-            // that the spread is below kIncSpan)
-            const int span = min(off[kIncK - 1] - lo, kIncSpan - 1);
+            const int span = off[kIncK - 1];             // < kIncSpan (clamped in the table)
             __syncthreads();
 #pragma unroll
             for (int m = 0; m < kPf; ++m)
                 win[lane + 64 * m] = pf[m];
             if (span >= 64 * kPf - kIncT) {             // rare: wide spread, load the rest now
-                const float *row = base + (long long)ch * a.ntime + lo;
-                const int last = room - lo;
+                const auto v = view(lo);
 #pragma unroll 1
                 for (int m = kPf; 64 * m < kIncT + span; ++m)
-                    win[lane + 64 * m] = row[min(lane + 64 * m, last)];
+                    win[lane + 64 * m] = inc_load(v, 4 * (lane + 64 * m));
             }
+            dk += a.kpad;
+            row += a.ntime;
             if (ch + 1 < a.nch) {
 #pragma unroll
                 for (int k = 0; k < kIncK; ++k)
-                    offn[k] = Dd[(long long)(ch + 1) * a.kpad + k];
-                const float *row = base + (long long)(ch + 1) * a.ntime + offn[0];
-                const int last = room - offn[0];
+                    offn[k] = dk[k];
+                const auto v = view(offn[0]);
 #pragma unroll
                 for (int m = 0; m < kPf; ++m)
-                    pf[m] = row[min(lane + 64 * m, last)];
+                    pf[m] = inc_load(v, 4 * (lane + 64 * m));
             }
             __syncthreads();
-            int held = -1;
+            int held = 0;
             float w[kIncS];
 #pragma unroll
             for (int k = 0; k < kIncK; ++k) {
-                const int o = min(off[k] - lo, span);
-                if (o != held) {
+                const int o = k == 0 ? 0 : off[k];
+                if (k == 0 || o != held) {
                     held = o;
 #pragma unroll
                     for (int j = 0; j < kIncS; ++j)
@@ -2342,7 +2358,14 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
                 for (int j = 0; j < kIncS; ++j)
                     inc_add(acc[k][j], w[j]);
             }
+        };
+        int ch = 0;
+        for (; ch + 1 < a.nch; ch += 2) {
+            step(ch, offa, offb);
+            step(ch + 1, offb, offa);
         }
+        if (ch < a.nch)
+            step(ch, offa, offb);
     }
     const int nk = min(kIncK, a.ntrial - kg);
 #pragma unroll
@@ -2451,6 +2474,7 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
     float *ft = static_cast<float *>(ws);
     const size_t ftb = (size_t)ndm * a.nch * a.ntime * sizeof(float);
     int *D = reinterpret_cast<int *>(static_cast<char *>(ws) + ((ftb + 255) & ~(size_t)255));
+    const bool narrow = a.ntrial == 1 || inc_narrow(a);
     for (int first = 0; first < ndm; first += kMaxDmPerLaunch) {
         const int cnt = ndm - first < kMaxDmPerLaunch ? ndm - first : kMaxDmPerLaunch;
         DmList dl;
@@ -2458,7 +2482,8 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
         for (int i = 0; i < cnt; ++i)
             dl.dm[i] = dm_coh[first + i];
         const long long n = (long long)cnt * a.kpad * a.nch;
-        inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt, D);
+        inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt,
+                                                              narrow ? kIncSpan - 1 : 0x7fffffff, D);
         if (hipGetLastError() != hipSuccess)
             return CDMT_E_DEVICE;
     }
@@ -2469,7 +2494,7 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
     const int ntile = (int)((a.nout + kIncT - 1) / kIncT);
     const int ngroup = a.kpad / kIncK;
     const unsigned grid = (unsigned)((long long)ndm * ntile * ngroup);
-    if (a.ntrial == 1 || inc_narrow(a))
+    if (narrow)
         inc_sum<false><<<grid, 64, 0, s>>>(ft, D, a, ntile, ngroup, out);
     else
         inc_sum<true><<<grid, 64, 0, s>>>(ft, D, a, ntile, ngroup, out);
