@@ -2152,16 +2152,17 @@ void cdmt_batch_destroy(cdmt_batch_t bt) {
 // DM steps around its trial, i.e. every channel's series is shifted by its
 // dispersion delay behind the highest channel (Eq. 2, in whole output
 // samples) and the channels are summed.
-//   inc_delays     delay table in FP64, rounded half to even, laid out
-//                  [d][ch][k] with the trial axis padded to a multiple of kIncK
-//                  (padding repeats the last trial): per group of kIncK trials
-//                  the first entry is the group's first delay and the others
-//                  are relative to it, so a workgroup reads what it needs for
-//                  a channel with one scalar load
+//   inc_delays     delay table in FP64, rounded half to even, in groups of
+//                  kIncK trials (padding repeats the last trial): per group
+//                  and channel the first delay, then the others relative to
+//                  it, as int32 laid out [d][ch][k] or, when every spread is
+//                  below kIncSpan, as bytes packed in 8 int32 laid out
+//                  [d][group][ch] (a channel pair is one 64-byte load)
 //   inc_transpose  [d][t][ch] -> [d][ch][t] through LDS, so that the sums
 //                  read each channel's series contiguously
 //   inc_sum        one wave per (coherent DM, kIncK fine trials, kIncT output
-//                  samples), each lane owning kIncS consecutive samples.  Per
+//                  samples), each lane owning kIncS samples 64 apart (so LDS
+//                  reads of consecutive lanes hit consecutive banks).  Per
 //                  channel the wave stages the window its trials read (the
 //                  tile plus the spread of their delays) in LDS once; the
 //                  delays grow with the trial index, so a lane re-reads its
@@ -2177,7 +2178,7 @@ struct IncArgs {
     double f_centre, bw, tsamp, ddm0, ddm;
 };
 
-constexpr int kIncS = 4;                      // consecutive samples per lane
+constexpr int kIncS = 4;                      // samples per lane, 64 apart
 constexpr int kIncT = 64 * kIncS;             // output samples per workgroup
 constexpr int kIncK = 16;                     // fine trials per workgroup
 constexpr int kIncSpan = 256;                 // widest delay spread staged in LDS
@@ -2201,22 +2202,38 @@ __host__ __device__ inline long long inc_delay(const IncArgs &a, double dm, int 
 }
 
 __global__ __launch_bounds__(256) void inc_delays(IncArgs a, DmList dl, int first, int cnt,
-                                                  int clamp, int *__restrict__ D) {
+                                                  int packed, int *__restrict__ D) {
 #pragma clang fp contract(off)
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    const long long per = (long long)a.nch * a.kpad;
+    const int ngroup = a.kpad / kIncK;
+    const long long per = (long long)a.nch * ngroup;
     if (i >= per * cnt)
         return;
     const int dl_i = (int)(i / per);
-    const int ch = (int)((i % per) / a.kpad);
-    const int kr = (int)(i % a.kpad);
-    const int k0 = kr - kr % kIncK;                // first trial of the group (< ntrial)
-    const int k = min(kr, a.ntrial - 1);
-    const double dm0 = dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)k0);
-    const double dm = dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)k);
-    const int lo = (int)inc_delay(a, dm0, ch);
-    const int v = kr == k0 ? lo : min((int)inc_delay(a, dm, ch) - lo, clamp);
-    D[(long long)(first + dl_i) * per + (i % per)] = v;
+    const int ch = (int)((i % per) / ngroup);
+    const int k0 = (int)(i % ngroup) * kIncK;       // first trial of the group (< ntrial)
+    const auto delay = [&](int k) {
+        return (int)inc_delay(a, dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)min(k, a.ntrial - 1)), ch);
+    };
+    const int lo = delay(k0);
+    if (packed) {
+        const long long npair = (a.nch + 1) / 2;
+        int *slot = D + (((long long)(first + dl_i) * ngroup + k0 / kIncK) * npair) * 16 + ch * 8;
+        unsigned b[4] = {0u, 0u, 0u, 0u};
+        for (int k = 1; k < kIncK; ++k)
+            b[k / 4] |= (unsigned)min(delay(k0 + k) - lo, kIncSpan - 1) << (8 * (k % 4));
+        slot[0] = lo;
+        for (int q = 0; q < 4; ++q)
+            slot[1 + q] = (int)b[q];
+        if (ch == a.nch - 1 && a.nch % 2)            // the all-zero channel completing the pair
+            for (int q = 8; q < 16; ++q)
+                slot[q] = 0;
+    } else {
+        int *slot = D + ((long long)(first + dl_i) * a.nch + ch) * a.kpad + k0;
+        slot[0] = lo;
+        for (int k = 1; k < kIncK; ++k)
+            slot[k] = delay(k0 + k) - lo;
+    }
 }
 
 __global__ __launch_bounds__(256) void inc_transpose(const float *__restrict__ fb,
@@ -2266,7 +2283,7 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
                                               const int *__restrict__ D, IncArgs a, int ntile,
                                               int ngroup, float *__restrict__ out) {
     constexpr int kPf = kIncT / 64 + 1;             // window loads per lane for spreads < 64
-    __shared__ float win[WIDE ? 1 : kIncT + kIncSpan];
+    __shared__ float win[WIDE ? 1 : 2][WIDE ? 1 : kIncT + kIncSpan];
     // XCD-aware order: the trial groups of one time tile run on one XCD
     // together and share its L2 copy of the tile's windows
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
@@ -2282,8 +2299,9 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
 #pragma unroll
         for (int j = 0; j < kIncS; ++j)
             acc[k][j] = 0.f;
-    // delays of channel ch: dk[0] = first trial's, dk[k] = trial k's minus it
-    const int *dk = D + d * a.nch * a.kpad + kg;
+    // this group's delays: [d][ch][k] (wide) or [d][group][channel pair][16]
+    const int *dk = WIDE ? D + d * a.nch * a.kpad + kg
+                         : D + ((d * ngroup + kgi) * ((a.nch + 1) / 2)) * 16;
     const float *row = ft + d * a.nch * a.ntime + t0;      // channel ch's series at t0
     const int room = (int)(a.ntime - 1 - t0);           // last readable offset from row
     if constexpr (WIDE) {
@@ -2295,87 +2313,124 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
                 const int o = k == 0 ? 0 : dk[k];
 #pragma unroll
                 for (int j = 0; j < kIncS; ++j)
-                    acc[k][j] += row[lo + min(kIncS * lane + o + j, last)];
+                    acc[k][j] += row[lo + min(lane + 64 * j + o, last)];
             }
         }
     } else {
-        // The next channel's delays and window are loaded while the current
-        // channel's trials are summed; the delays alternate between two
-        // arrays (channel pairs) so that none are copied.  view(lo) covers
-        // the kIncT + kIncSpan samples from a channel's first delay on (fewer
-        // at the end of the series).
-        const auto view = [&](int lo) {
-            return inc_view(row + lo, min(room - lo + 1, kIncT + kIncSpan));
+        // Channels go in pairs whose trial sums interleave, so that the two
+        // windows' LDS reads overlap.  A pair's delays (per channel: the first
+        // delay and 15 byte offsets packed in 4 words, padded to 8 words) are
+        // one 64-byte scalar load, issued two pairs ahead; its windows are
+        // loaded one pair ahead, while the current pair's trials are summed.
+        // The delays rotate through three arrays, so that none are copied.
+        // view(r, lo) covers the kIncT + kIncSpan samples of series r from
+        // delay lo on (fewer at the end of the series).
+        const auto view = [&](const float *r, int lo) {
+            return inc_view(r + lo, min(room - lo + 1, kIncT + kIncSpan));
         };
-        int offa[kIncK], offb[kIncK];
-        float pf[kPf];
-#pragma unroll
-        for (int k = 0; k < kIncK; ++k)
-            offa[k] = dk[k];
-        {
-            const auto v = view(offa[0]);
-#pragma unroll
-            for (int m = 0; m < kPf; ++m)
-                pf[m] = inc_load(v, 4 * (lane + 64 * m));
-        }
-        const auto step = [&](int ch, const int (&off)[kIncK], int (&offn)[kIncK]) {
-            const int lo = off[0];
-            const int span = off[kIncK - 1];             // < kIncSpan (clamped in the table)
-            __syncthreads();
+        const auto offset = [](const int (&dl)[16], int c, int k) {
+            return k == 0 ? 0 : (int)(((unsigned)dl[8 * c + 1 + k / 4] >> (8 * (k % 4))) & 0xffu);
+        };
+        // stage channel c of a pair in LDS buffer c: the kPf loads in pf plus,
+        // for spreads of 64 or more, the rest loaded now
+        const auto stage = [&](int c, const int (&dl)[16], const float (&pf)[kPf]) {
 #pragma unroll
             for (int m = 0; m < kPf; ++m)
-                win[lane + 64 * m] = pf[m];
-            if (span >= 64 * kPf - kIncT) {             // rare: wide spread, load the rest now
-                const auto v = view(lo);
+                win[c][lane + 64 * m] = pf[m];
+            const int span = offset(dl, c, kIncK - 1);
+            if (span >= 64 * kPf - kIncT) {
+                const auto v = view(row + c * a.ntime, dl[8 * c]);
 #pragma unroll 1
                 for (int m = kPf; 64 * m < kIncT + span; ++m)
-                    win[lane + 64 * m] = inc_load(v, 4 * (lane + 64 * m));
+                    win[c][lane + 64 * m] = inc_load(v, 4 * (lane + 64 * m));
             }
-            dk += a.kpad;
-            row += a.ntime;
-            if (ch + 1 < a.nch) {
-#pragma unroll
-                for (int k = 0; k < kIncK; ++k)
-                    offn[k] = dk[k];
-                const auto v = view(offn[0]);
+        };
+        // window loads of channel c of the pair at r (a missing second
+        // channel of an odd count is all zero: adding +0 changes no sum)
+        const auto fetch = [&](bool real, const float *r, int lo, float (&pf)[kPf]) {
+            if (real) {
+                const auto v = view(r, lo);
 #pragma unroll
                 for (int m = 0; m < kPf; ++m)
                     pf[m] = inc_load(v, 4 * (lane + 64 * m));
-            }
-            __syncthreads();
-            int held = 0;
-            float w[kIncS];
+            } else {
 #pragma unroll
-            for (int k = 0; k < kIncK; ++k) {
-                const int o = k == 0 ? 0 : off[k];
-                if (k == 0 || o != held) {
-                    held = o;
-#pragma unroll
-                    for (int j = 0; j < kIncS; ++j)
-                        w[j] = win[kIncS * lane + o + j];
-                }
-#pragma unroll
-                for (int j = 0; j < kIncS; ++j)
-                    inc_add(acc[k][j], w[j]);
+                for (int m = 0; m < kPf; ++m)
+                    pf[m] = 0.f;
             }
         };
-        int ch = 0;
-        for (; ch + 1 < a.nch; ch += 2) {
-            step(ch, offa, offb);
-            step(ch + 1, offb, offa);
+        const auto delays = [&](int p, int (&dl)[16]) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q)
+                dl[q] = dk[16 * p + q];
+        };
+        // trial sums of the two staged channels, channel by channel per trial
+        const auto sums = [&](const int (&dl)[16]) {
+            int held[2];
+            float w[2][kIncS];
+#pragma unroll
+            for (int k = 0; k < kIncK; ++k) {
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const int o = offset(dl, c, k);
+                    if (k == 0 || o != held[c]) {
+                        held[c] = o;
+#pragma unroll
+                        for (int j = 0; j < kIncS; ++j)
+                            w[c][j] = win[c][lane + 64 * j + o];
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int j = 0; j < kIncS; ++j)
+                        inc_add(acc[k][j], w[c][j]);
+            }
+        };
+        const int npair = (a.nch + 1) / 2;
+        int dla[16], dlb[16], dlc[16];
+        float pf[2][kPf];
+        delays(0, dla);
+        if (npair > 1)
+            delays(1, dlb);
+        fetch(true, row, dla[0], pf[0]);
+        fetch(a.nch > 1, row + a.ntime, dla[8], pf[1]);
+        // pair p: delays in cur, the next pair's in nxt, pair p + 2's loaded
+        // into far
+        const auto pair = [&](int p, const int (&cur)[16], const int (&nxt)[16], int (&far)[16]) {
+            __syncthreads();
+            stage(0, cur, pf[0]);
+            stage(1, cur, pf[1]);
+            row += 2 * a.ntime;
+            if (p + 1 < npair) {
+                fetch(true, row, nxt[0], pf[0]);
+                fetch(2 * p + 3 < a.nch, row + a.ntime, nxt[8], pf[1]);
+            }
+            if (p + 2 < npair)
+                delays(p + 2, far);
+            __syncthreads();
+            sums(cur);
+        };
+        int p = 0;
+        for (; p + 2 < npair; p += 3) {
+            pair(p, dla, dlb, dlc);
+            pair(p + 1, dlb, dlc, dla);
+            pair(p + 2, dlc, dla, dlb);
         }
-        if (ch < a.nch)
-            step(ch, offa, offb);
+        if (p < npair)
+            pair(p, dla, dlb, dlc);
+        if (p + 1 < npair)
+            pair(p + 1, dlb, dlc, dla);
     }
     const int nk = min(kIncK, a.ntrial - kg);
 #pragma unroll
     for (int k = 0; k < kIncK; ++k) {
         if (k < nk) {
-            float *o = out + (d * a.ntrial + kg + k) * a.nout + t0 + kIncS * lane;
+            float *o = out + (d * a.ntrial + kg + k) * a.nout + t0 + lane;
 #pragma unroll
             for (int j = 0; j < kIncS; ++j)
-                if (t0 + kIncS * lane + j < a.nout)
-                    o[j] = acc[k][j];
+                if (t0 + lane + 64 * j < a.nout)
+                    o[64 * j] = acc[k][j];
         }
     }
 }
@@ -2481,9 +2536,9 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
         std::memset(&dl, 0, sizeof(dl));
         for (int i = 0; i < cnt; ++i)
             dl.dm[i] = dm_coh[first + i];
-        const long long n = (long long)cnt * a.kpad * a.nch;
-        inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt,
-                                                              narrow ? kIncSpan - 1 : 0x7fffffff, D);
+        const long long n = (long long)cnt * (a.kpad / kIncK) * a.nch;
+        inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt, narrow ? 1 : 0,
+                                                              D);
         if (hipGetLastError() != hipSuccess)
             return CDMT_E_DEVICE;
     }

@@ -43,6 +43,7 @@ CASES = {
     "one-trial-dm0": (oracle.CHANNEL, [0.5, 2.0], -0.5, 0.0, 1),
     "spread-over-64": (oracle.CHANNEL, [0.0, 1.0], 0.0, 0.5, 16),
     "coarse-global": (oracle.CHANNEL, [1.0, 2.0], 0.0, 2.0, 10),
+    "odd-channels": (oracle.CHANNEL, [1.0, 4.0], -0.5, 0.05, 20),
 }
 
 
@@ -54,6 +55,10 @@ def test_incoherent_parity(hip_lib, name, kind):
     # 384 samples: several 256-sample tiles and a ragged tail
     cfg = oracle.Config(4, 140.0, synth.SUBBAND_MHZ, 16384, 4096, 8, 4, chirp_ref=mode)
     nblock = 4
+    if name == "odd-channels":
+        # 3 subbands of one channel each (an odd channel count), 81.92 us samples
+        cfg = oracle.Config(3, 140.0, synth.SUBBAND_MHZ, 4096, 1024, 1, 16, chirp_ref=mode)
+        nblock = 2
     ntime = nblock * cfg.tblk
     nch = cfg.nsub * cfg.nchan
     print(f"[gpu-case] incoherent {name} {kind}", flush=True)
