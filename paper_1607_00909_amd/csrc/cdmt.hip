@@ -2159,7 +2159,8 @@ void cdmt_batch_destroy(cdmt_batch_t bt) {
 //                  below kIncSpan, as bytes packed in 8 int32 laid out
 //                  [d][group][ch] (a channel pair is one 64-byte load)
 //   inc_transpose  [d][t][ch] -> [d][ch][t] through LDS, so that the sums
-//                  read each channel's series contiguously
+//                  read each channel's series contiguously (64 x 64 tiles
+//                  moved as float4 where the sizes allow, else 32 x 32)
 //   inc_sum        one wave per (coherent DM, kIncK fine trials, kIncT output
 //                  samples), each lane owning kIncS samples 64 apart (so LDS
 //                  reads of consecutive lanes hit consecutive banks).  Per
@@ -2233,6 +2234,39 @@ __global__ __launch_bounds__(256) void inc_delays(IncArgs a, DmList dl, int firs
         slot[0] = lo;
         for (int k = 1; k < kIncK; ++k)
             slot[k] = delay(k0 + k) - lo;
+    }
+}
+
+// 64 x 64 tiles moved as float4 (nch and ntime multiples of 4)
+__global__ __launch_bounds__(256) void inc_transpose4(const float *__restrict__ fb,
+                                                      float *__restrict__ ft, long long ntime,
+                                                      int nch) {
+    __shared__ float tile[64][65];
+    const long long t0 = (long long)blockIdx.x * 64;
+    const int c0 = blockIdx.y * 64;
+    const long long d = blockIdx.z;
+    const int q = (threadIdx.x % 16) * 4, r0 = threadIdx.x / 16;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int r = r0 + 16 * p;
+        const long long t = t0 + r;
+        if (t < ntime && c0 + q < nch) {
+            const float4 v = *reinterpret_cast<const float4 *>(fb + (d * ntime + t) * nch + c0 + q);
+            tile[r][q] = v.x;
+            tile[r][q + 1] = v.y;
+            tile[r][q + 2] = v.z;
+            tile[r][q + 3] = v.w;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        const int r = r0 + 16 * p;
+        const long long t = t0 + q;
+        if (c0 + r < nch && t < ntime) {
+            const float4 v = {tile[q][r], tile[q + 1][r], tile[q + 2][r], tile[q + 3][r]};
+            *reinterpret_cast<float4 *>(ft + (d * nch + c0 + r) * ntime + t) = v;
+        }
     }
 }
 
@@ -2542,8 +2576,13 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
         if (hipGetLastError() != hipSuccess)
             return CDMT_E_DEVICE;
     }
-    inc_transpose<<<dim3((unsigned)tiles_t, (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256, 0,
-                    s>>>(fb, ft, a.ntime, a.nch);
+    if (a.nch % 4 == 0 && a.ntime % 4 == 0 && reinterpret_cast<uintptr_t>(fb) % 16 == 0 &&
+        reinterpret_cast<uintptr_t>(ft) % 16 == 0)
+        inc_transpose4<<<dim3((unsigned)((a.ntime + 63) / 64), (unsigned)((a.nch + 63) / 64),
+                              (unsigned)ndm), 256, 0, s>>>(fb, ft, a.ntime, a.nch);
+    else
+        inc_transpose<<<dim3((unsigned)tiles_t, (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256,
+                        0, s>>>(fb, ft, a.ntime, a.nch);
     if (hipGetLastError() != hipSuccess)
         return CDMT_E_DEVICE;
     const int ntile = (int)((a.nout + kIncT - 1) / kIncT);
