@@ -51,7 +51,7 @@ def measured_traffic(kernel: str):
     except (OSError, AttributeError, ValueError):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_1607_00909_amd", "csrc", f), "rb").read()
-                   for f in ("cdmt.hip", "fft_core.hpp"))
+                   for f in ("cdmt.hip", "fft_core.hpp", "plan.hpp"))
     if hashlib.sha256(src).hexdigest()[:16] != blob.get("source_sha256_16"):
         return None
     t = blob["traffic"].get(kernel)

@@ -10,8 +10,9 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", "cdmt.hip"), os.path.join(HERE, "csrc", "redigit.hip")]
-DEPS = [*SRCS, os.path.join(HERE, "csrc", "fft_core.hpp"), os.path.join(ROOT, "include", "cdmt.h")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("cdmt.hip", "redigit.hip", "incoherent.hip")]
+DEPS = [*SRCS, os.path.join(HERE, "csrc", "fft_core.hpp"), os.path.join(HERE, "csrc", "plan.hpp"),
+        os.path.join(ROOT, "include", "cdmt.h")]
 LIB = os.path.join(HERE, "libcdmt.so")
 ARCH = os.environ.get("CDMT_OFFLOAD_ARCH", "gfx950")
 
