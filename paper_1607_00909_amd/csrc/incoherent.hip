@@ -112,35 +112,44 @@ __global__ __launch_bounds__(256) void inc_delays(IncArgs a, IncDms dl, int firs
     }
 }
 
-// 64 x 64 tiles moved as float4 (nch and ntime multiples of 4)
+// TC channels x TT samples per tile, moved as float4 (nch and ntime
+// multiples of 4): reads of TC channels per time row, writes of TT samples
+// per channel row
+template <int TC, int TT>
 __global__ __launch_bounds__(256) void inc_transpose4(const float *__restrict__ fb,
                                                       float *__restrict__ ft, long long ntime,
                                                       int nch) {
-    __shared__ float tile[64][65];
-    const long long t0 = (long long)blockIdx.x * 64;
-    const int c0 = blockIdx.y * 64;
+    __shared__ float tile[TT][TC + 1];
+    const long long t0 = (long long)blockIdx.x * TT;
+    const int c0 = blockIdx.y * TC;
     const long long d = blockIdx.z;
-    const int q = (threadIdx.x % 16) * 4, r0 = threadIdx.x / 16;
+    constexpr int RQ = TC / 4, RP = 256 / RQ;       // read: float4 per row, rows per pass
+    constexpr int WQ = TT / 4, WP = 256 / WQ;       // write: float4 per row, rows per pass
+    {
+        const int q = (threadIdx.x % RQ) * 4, r0 = threadIdx.x / RQ;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int r = r0 + 16 * p;
-        const long long t = t0 + r;
-        if (t < ntime && c0 + q < nch) {
-            const float4 v = *reinterpret_cast<const float4 *>(fb + (d * ntime + t) * nch + c0 + q);
-            tile[r][q] = v.x;
-            tile[r][q + 1] = v.y;
-            tile[r][q + 2] = v.z;
-            tile[r][q + 3] = v.w;
+        for (int r = r0; r < TT; r += RP) {
+            const long long t = t0 + r;
+            if (t < ntime && c0 + q < nch) {
+                const float4 v =
+                    *reinterpret_cast<const float4 *>(fb + (d * ntime + t) * nch + c0 + q);
+                tile[r][q] = v.x;
+                tile[r][q + 1] = v.y;
+                tile[r][q + 2] = v.z;
+                tile[r][q + 3] = v.w;
+            }
         }
     }
     __syncthreads();
+    {
+        const int q = (threadIdx.x % WQ) * 4, r0 = threadIdx.x / WQ;
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int r = r0 + 16 * p;
-        const long long t = t0 + q;
-        if (c0 + r < nch && t < ntime) {
-            const float4 v = {tile[q][r], tile[q + 1][r], tile[q + 2][r], tile[q + 3][r]};
-            *reinterpret_cast<float4 *>(ft + (d * nch + c0 + r) * ntime + t) = v;
+        for (int r = r0; r < TC; r += WP) {
+            const long long t = t0 + q;
+            if (c0 + r < nch && t < ntime) {
+                const float4 v = {tile[q][r], tile[q + 1][r], tile[q + 2][r], tile[q + 3][r]};
+                *reinterpret_cast<float4 *>(ft + (d * nch + c0 + r) * ntime + t) = v;
+            }
         }
     }
 }
@@ -453,8 +462,9 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
     }
     if (a.nch % 4 == 0 && a.ntime % 4 == 0 && reinterpret_cast<uintptr_t>(fb) % 16 == 0 &&
         reinterpret_cast<uintptr_t>(ft) % 16 == 0)
-        inc_transpose4<<<dim3((unsigned)((a.ntime + 63) / 64), (unsigned)((a.nch + 63) / 64),
-                              (unsigned)ndm), 256, 0, s>>>(fb, ft, a.ntime, a.nch);
+        inc_transpose4<32, 256><<<dim3((unsigned)((a.ntime + 255) / 256),
+                                       (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256, 0,
+                                  s>>>(fb, ft, a.ntime, a.nch);
     else
         inc_transpose<<<dim3((unsigned)tiles_t, (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256,
                         0, s>>>(fb, ft, a.ntime, a.nch);
