@@ -36,22 +36,24 @@ VALU_FP32_PACKED_PEAK_TFLOPS = 2 * VALU_FP32_PEAK_TFLOPS
 
 
 PROFILE = os.path.join(ROOT, "profiles", "fused_dedisperse_lofar_hba_288sub_128dm.md")
+PROFILE_INC = os.path.join(ROOT, "profiles", "inc_sum_lofar_hba_40dm_500trials.md")
 # dense FP16 / BF16 matrix-core peak of the MI355X (no sparsity)
 MFMA_F16_PEAK_TFLOPS = 2500.0
 
 
-def measured_traffic(kernel: str):
+def measured_traffic(kernel: str, profile: str = PROFILE,
+                     sources=("cdmt.hip", "fft_core.hpp", "plan.hpp")):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary, or None when the kernel sources changed since it was taken."""
     import hashlib
     import re
     try:
-        text = open(PROFILE).read()
+        text = open(profile).read()
         blob = json.loads(re.search(r"```json\n(.*?)\n```", text, re.S).group(1))
     except (OSError, AttributeError, ValueError):
         return None
     src = b"".join(open(os.path.join(ROOT, "paper_1607_00909_amd", "csrc", f), "rb").read()
-                   for f in ("cdmt.hip", "fft_core.hpp", "plan.hpp"))
+                   for f in sources)
     if hashlib.sha256(src).hexdigest()[:16] != blob.get("source_sha256_16"):
         return None
     t = blob["traffic"].get(kernel)
@@ -251,13 +253,16 @@ def incoherent_leg(cdmt, torch, plan, w, out, dms, steps: int):
     tsamp = w.nchan * w.ndec / (w.bw * 1e6)
     adds = len(dm_coh) * ntrial * nout * nch
     adds_peak = 256 * 64 * 2.4e9                 # FP32 adds per second, one per lane per clock
+    traffic = measured_traffic("inc_sum<false>", PROFILE_INC, ("incoherent.hip", "plan.hpp"))
     del iws, iout
     return {"ms": round(ms, 3), "coherent_dms": len(dm_coh), "fine_trials": ntrial,
             "nout": nout,
             "trial_seconds_per_s": round(len(dm_coh) * ntrial * nout * tsamp / (ms / 1e3), 1),
             "roofline": {"bound": "alu", "achieved": round(adds / (ms / 1e3) / 1e12, 2),
                          "peak": round(adds_peak / 1e12, 2), "unit": "Tadd/s",
-                         "frac": round(adds / (ms / 1e3) / adds_peak, 4)}}
+                         "frac": round(adds / (ms / 1e3) / adds_peak, 4),
+                         "traffic": traffic,
+                         "note": "whole call (delays, transpose, sums) timed; sums alone in profiles/"}}
 
 
 def main():
