@@ -223,6 +223,25 @@ def gradient_leg(cdmt, synth, torch, dev, steps: int):
             "gradient_dm_s_per_s": round(len(dms) * data_s / (adj / 1e3), 1)}
 
 
+def copy_bandwidth(torch, dev, nbytes: int = 4 << 30, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (bytes read + written per second):
+    the practical HBM ceiling that the kernels are also compared with."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    rate = 2 * nbytes * reps / (ev[0].elapsed_time(ev[1]) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return rate
+
+
 def incoherent_leg(cdmt, torch, plan, w, out, dms, steps: int):
     """The semi-coherent search's incoherent stage on the coherent output:
     the 40 filterbanks at DM 0.5..20 (of the 128), each dedispersed
@@ -344,6 +363,9 @@ def main():
         log("calibration copy: 1 GiB read, 1 GiB written")
         del src, dst
 
+    copy_gbs = copy_bandwidth(torch, dev) / 1e9
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write)")
+
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -398,9 +420,11 @@ def main():
                      "traffic": measured_traffic("fused_dedisperse<%d>" % w.m),
                      "hbm_algorithmic_GBs": round(fused_bytes / fus_avg / 1e9, 1),
                      "hbm_frac": round(fused_bytes / fus_avg / 1e9 / HBM_PEAK_GBS, 4)},
+        "hbm_copy_GBs": round(copy_gbs, 1),
         "kernels_ms": {"forward (fwd_col+fwd_row)": round(fwd_avg * 1e3, 3),
                        "fused_dedisperse": round(fus_avg * 1e3, 3),
-                       "forward_algorithmic_GBs": round(fwd_bytes / fwd_avg / 1e9, 1)},
+                       "forward_algorithmic_GBs": round(fwd_bytes / fwd_avg / 1e9, 1),
+                       "forward_frac_of_copy": round(fwd_bytes / fwd_avg / 1e9 / copy_gbs, 4)},
         "realtime_factor": round(w.data_seconds / (elapsed / args.steps), 2),
     }
     outputs = {args.precision: out}
@@ -466,7 +490,8 @@ def main():
         rbytes = 2 * out.numel() * 4 + out.numel() + 2 * rws.numel()
         line["redigitise"] = {"ms": round(rms, 3), "bound": "hbm",
                               "algorithmic_GBs": round(rbytes / rms / 1e6, 1),
-                              "hbm_frac": round(rbytes / rms / 1e6 / HBM_PEAK_GBS, 4)}
+                              "hbm_frac": round(rbytes / rms / 1e6 / HBM_PEAK_GBS, 4),
+                              "frac_of_copy": round(rbytes / rms / 1e6 / copy_gbs, 4)}
         log(f"redigitise: {rms:.3f} ms")
         del codes, rws
     if args.incoherent:

@@ -133,6 +133,59 @@ def test_autograd_refines_an_off_grid_dm(hip_lib):
     assert L > L0 and abs(dm - dm_true) < 0.02
 
 
+def _snr_np(F, t0):
+    """S/N of the channel-summed series s at sample t0: (s[t0] - mean) / std
+    (population std).  A median/MAD form is not smooth in DM: its order
+    statistics swap every few 1e-5 pc cm^-3, so differences at 1e-4 would
+    straddle kinks."""
+    s = F.sum(axis=1)
+    return (s[t0] - s.mean()) / s.std()
+
+
+def test_snr_gradient_matches_oracle_differences(hip_lib):
+    """d(S/N)/dDM through the autograd function (S/N of the channel-summed
+    series at the pulse sample, formed in torch) against central differences
+    at 1e-4 pc cm^-3 of the same S/N of the oracle's FP64 filterbank.  (DM
+    refinement by ascent is the power test above: this S/N at one sample has
+    side maxima from the intra-channel smearing, and with a bright pulse it
+    saturates near sqrt(n).)"""
+    torch = _torch()
+    print("[gpu-case] d(S/N)/dDM", flush=True)
+    nsub, fc, nfft, nov, nchan, ndec, nblock = 8, 120.78125, 16384, 4096, 8, 4, 2
+    cfg = oracle.Config(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec,
+                        chirp_ref=oracle.SUBBAND)
+    x = synth.gaussian_voltages(nsub, cfg.ntime_in(nblock), 0.5, 23)
+    t0 = cfg.tblk + 100
+    dm_true = 10.37
+    for s in range(nsub):
+        oracle.inject_impulse(cfg, x, s, dm_true, oracle.pulse_sample(cfg, t0), 20.0)
+    v = synth.encode_cf32(x)
+    plan = hip_lib.Plan(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec,
+                        chirp_ref=hip_lib.CHIRP_SUBBAND, chirp_exact=1)
+    ws = plan.workspace(nblock)
+    plan.forward(torch.from_numpy(v).cuda(), nblock, ws)
+
+    def snr_and_grad(dm):
+        d = torch.tensor([dm], dtype=torch.float64, requires_grad=True)
+        F = hip_lib.dedisperse_dm(plan, d, nblock, ws)
+        s = F[0].double().sum(dim=1)
+        snr = (s[t0] - s.mean()) / s.std(correction=0)
+        snr.backward()
+        return float(snr.detach()), float(d.grad[0])
+
+    h = 1e-4
+    for dm in (10.0, 10.2):
+        S, g = snr_and_grad(dm)
+        Sp = _snr_np(oracle.dedisperse(cfg, v, nblock, [dm + h])[0], t0)
+        Sm = _snr_np(oracle.dedisperse(cfg, v, nblock, [dm - h])[0], t0)
+        S0 = _snr_np(oracle.dedisperse(cfg, v, nblock, [dm])[0], t0)
+        fd = (Sp - Sm) / (2 * h)
+        print(f"DM {dm}: S/N gpu {S:.6f} oracle {S0:.6f}; d(S/N)/dDM autograd {g:.6e}, "
+              f"oracle differences {fd:.6e}", flush=True)
+        assert abs(S - S0) <= 1e-5 * abs(S0)
+        assert abs(g - fd) <= 1e-4 * abs(fd)
+
+
 @pytest.mark.parametrize("mode", [oracle.CHANNEL, oracle.SUBBAND], ids=["channel", "subband"])
 def test_voltage_gradient_matches_oracle(hip_lib, mode):
     """dL/dvoltage for one DM against the oracle (normwise per subband), the
