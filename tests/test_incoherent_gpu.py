@@ -123,3 +123,26 @@ def test_incoherent_lofar_scale_samples(hip_lib):
             worst = max(worst, float(err.max()))
     print(f"lofar-scale: max err / bound {worst:.3f}", flush=True)
     assert worst <= 1.0
+
+
+@pytest.mark.parametrize("kind", ["codes", "power"])
+def test_incoherent_edges(hip_lib, kind):
+    """A largest delay that leaves exactly one output sample, and more than
+    256 coherent DMs (the delay table in several launches)."""
+    cfg = oracle.Config(4, 140.0, synth.SUBBAND_MHZ, 16384, 4096, 8, 4)
+    nblock = 2
+    nch = cfg.nsub * cfg.nchan
+    ntime = nblock * cfg.tblk
+    print(f"[gpu-case] incoherent edges {kind}", flush=True)
+    # DM 54.87: the lowest channel's delay is 767 of 768 samples
+    for dms, ddm0, ddm, ntrial in (([54.87], 0.0, 0.0, 1), ([54.0], 0.0, 0.87 / 2, 3),
+                                   ([0.05 * i for i in range(300)], 0.0, 0.01, 2)):
+        fb = synth.filterbank(len(dms), ntime, nch, 7 + ntrial, kind)
+        ref = incoherent.dedisperse(cfg, fb, dms, ddm0, ddm, ntrial)
+        gpu = _run(hip_lib, cfg, nblock, fb, dms, ddm0, ddm, ntrial)
+        assert gpu.shape == ref.shape
+        if kind == "codes":
+            assert np.array_equal(gpu.astype(np.float64), ref)
+        else:
+            assert np.all(np.abs(gpu.astype(np.float64) - ref) <= _gamma(nch - 1) * ref)
+    assert ref.shape[0] == 300
