@@ -570,9 +570,9 @@ def incoherent(plan, fb, nblock, dm_coh, ddm0, ddm, ntrial, out=None, workspace=
     nout = cdmt_incoherent_shape(plan.handle, nblock, dm_coh, ddm0, ddm, ntrial)
     if out is None:
         out = torch.empty((ndm, ntrial, nout), dtype=torch.float32, device=fb.device)
-    elif (out.dtype != torch.float32 or not out.is_contiguous()
+    elif (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
           or tuple(out.shape) != (ndm, ntrial, nout)):
-        raise ValueError(f"out must be a contiguous float32 tensor {(ndm, ntrial, nout)}")
+        raise ValueError(f"out must be a contiguous float32 device tensor {(ndm, ntrial, nout)}")
     if workspace is None:
         workspace = torch.empty(max(1, cdmt_incoherent_workspace_size(plan.handle, nblock, ndm,
                                                                       ntrial)),
