@@ -131,7 +131,8 @@ def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
     """The batched workload: 24 beams, each with its own subbands, N_bin,
     channels, overlap, DM list and output, in one persistent DM-stage launch
     per M_bin (all beams here have M_bin = 4096: one launch), replayed as a
-    hipGraph after the autotuner picked the DM tile and the grid."""
+    hipGraph after the autotuner picked each beam's forward-FFT split, the DM
+    tile and the grid."""
     import math
     draws = synth.batch_draws()
     beams, dm_seconds = [], 0.0
@@ -167,6 +168,10 @@ def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
            "items": batch.get(cdmt.CDMT_BATCH_ITEMS),
            "dm_tile": batch.get(cdmt.CDMT_BATCH_DM_TILE),
            "wg_per_cu": batch.get(cdmt.CDMT_BATCH_WG_PER_CU),
+           "forward_n2_changed": sum(
+               batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_FWD_N2) !=
+               cdmt.cdmt_plan_get(b[0].handle, cdmt.CDMT_OPT_FWD_N2)
+               for i, b in enumerate(beams)),
            "autotune_best_ms": round(tuned_ms, 3), "autotune_s": round(tune_s, 1),
            "graph": True}
     log(f"batch: {len(draws)} beams, {ms:.3f} ms per run, {res['value']} DM-s/s")

@@ -54,9 +54,15 @@ enum cdmt_opt {
                                 0 (default): when the DM list is an arithmetic
                                 progression, advance it by one complex factor per DM
                                 inside a tile (both factors from FP64 sincospi)        */
-    CDMT_OPT_LANE_BINS = 6   /* performance knob of the DM stage: spectral bins held per
+    CDMT_OPT_LANE_BINS = 6,  /* performance knob of the DM stage: spectral bins held per
                                 GPU lane, 16 (default) or 8 (twice the lanes per channel,
                                 half the registers; used for M_bin = 2048 and 4096)      */
+    CDMT_OPT_FWD_N2 = 7      /* radix schedule of the forward FFT: the four-step split
+                                N_bin = N1 * N2 with column transforms of N2 in
+                                {64, 128, 256} and row transforms of N1 = N_bin / N2 in
+                                [64, 512] (CDMT_E_ARG otherwise); default N2 =
+                                2^floor(log2(N_bin) / 2).  Splits give the same spectra
+                                up to FP32 rounding                                     */
 };
 
 /*
@@ -264,6 +270,16 @@ int cdmt_batch_create(cdmt_batch_t *out, const cdmt_beam_t *beams, int nbeam, vo
 int cdmt_batch_set(cdmt_batch_t batch, int opt, int value);
 int cdmt_batch_get(cdmt_batch_t batch, int opt, long long *value);
 
+/* Per-beam settings of a batch (enum cdmt_batch_beam_opt), beam = index in
+ * the creation order.  CDMT_BATCH_BEAM_FWD_N2: the forward FFT's split for
+ * that beam (as CDMT_OPT_FWD_N2; set 0 to use the beam plan's own); the
+ * beam's plan is not modified. */
+enum cdmt_batch_beam_opt {
+    CDMT_BATCH_BEAM_FWD_N2 = 0
+};
+int cdmt_batch_beam_set(cdmt_batch_t batch, int beam, int opt, int value);
+int cdmt_batch_beam_get(cdmt_batch_t batch, int beam, int opt, int *value);
+
 /* Enqueue the whole batch on hip_stream (NULL = default stream). */
 int cdmt_batch_run(cdmt_batch_t batch, void *hip_stream);
 
@@ -273,10 +289,13 @@ int cdmt_batch_run(cdmt_batch_t batch, void *hip_stream);
  * nodes (the queue counters are cleared by a kernel). */
 int cdmt_batch_run_graph(cdmt_batch_t batch, void *hip_stream);
 
-/* Time the batch on hip_stream for every DM tile in {4, 8, 16} and 2 or 4
- * workgroups per CU (reps runs each after one warm-up), keep the fastest
- * setting and return its time per run in *best_ms (may be NULL).  Writes the
- * beams' outputs. */
+/* Autotune the batch on hip_stream.  First the radix schedule of each
+ * beam's forward FFT: every valid split N1 x N2 (CDMT_OPT_FWD_N2) of the
+ * beam's N_bin is timed on that beam's forward stage alone and the fastest
+ * kept (CDMT_BATCH_BEAM_FWD_N2).  Then the whole batch for every DM tile in
+ * {4, 8, 16} and 2 or 4 workgroups per CU; the fastest setting is kept and
+ * its time per run returned in *best_ms (may be NULL).  reps runs per
+ * candidate after one warm-up.  Writes the beams' outputs. */
 int cdmt_batch_autotune(cdmt_batch_t batch, void *hip_stream, int reps, float *best_ms);
 
 /* Free a batch and its graph (NULL is accepted). */

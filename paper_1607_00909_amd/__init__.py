@@ -23,7 +23,7 @@ CDMT_OK, CDMT_E_ARG, CDMT_E_SHAPE, CDMT_E_WORKSPACE, CDMT_E_DEVICE, CDMT_E_UNSUP
     0, -1, -2, -3, -4, -5
 # enum cdmt_opt
 CDMT_OPT_INPUT, CDMT_OPT_CHIRP_REF, CDMT_OPT_SIGN, CDMT_OPT_PRECISION, CDMT_OPT_DM_TILE, \
-    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS = 0, 1, 2, 3, 4, 5, 6
+    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS, CDMT_OPT_FWD_N2 = 0, 1, 2, 3, 4, 5, 6, 7
 INPUT_CF32, INPUT_CI8 = 0, 1
 CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
 
@@ -34,11 +34,14 @@ EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
            "cdmt_redigitise_workspace_size", "cdmt_redigitise",
            "cdmt_batch_workspace_size", "cdmt_batch_create", "cdmt_batch_set", "cdmt_batch_get",
            "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy",
+           "cdmt_batch_beam_set", "cdmt_batch_beam_get",
            "cdmt_gradient_workspace_size", "cdmt_dm_gradient",
            "cdmt_voltage_gradient_workspace_size", "cdmt_voltage_gradient",
            "cdmt_incoherent_shape", "cdmt_incoherent_workspace_size", "cdmt_incoherent")
 # enum cdmt_batch_opt
 CDMT_BATCH_DM_TILE, CDMT_BATCH_WG_PER_CU, CDMT_BATCH_ITEMS, CDMT_BATCH_LAUNCHES = 0, 1, 2, 3
+# enum cdmt_batch_beam_opt
+CDMT_BATCH_BEAM_FWD_N2 = 0
 
 
 class Beam(ctypes.Structure):
@@ -106,6 +109,8 @@ def load():
         lib.cdmt_batch_run.argtypes = [P, P]
         lib.cdmt_batch_run_graph.argtypes = [P, P]
         lib.cdmt_batch_autotune.argtypes = [P, P, I, ctypes.POINTER(F)]
+        lib.cdmt_batch_beam_set.argtypes = [P, I, I, I]
+        lib.cdmt_batch_beam_get.argtypes = [P, I, I, ctypes.POINTER(I)]
         lib.cdmt_batch_destroy.argtypes = [P]
         lib.cdmt_batch_destroy.restype = None
         for name in EXPORTS:
@@ -477,6 +482,15 @@ class Batch:
     def autotune(self, stream=None, reps=2):
         return cdmt_batch_autotune(self.handle, self._stream(stream), reps)
 
+    def beam_set(self, beam, opt, value):
+        _check(load().cdmt_batch_beam_set(self.handle, beam, opt, value), "cdmt_batch_beam_set")
+
+    def beam_get(self, beam, opt):
+        v = ctypes.c_int()
+        _check(load().cdmt_batch_beam_get(self.handle, beam, opt, ctypes.byref(v)),
+               "cdmt_batch_beam_get")
+        return v.value
+
 
 # ------------------------------------------------- torch-facing wrapper ----
 
@@ -485,7 +499,7 @@ class Plan:
 
     def __init__(self, nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec, *,
                  input_kind=INPUT_CF32, chirp_ref=CHIRP_CHANNEL, sign=-1, dm_tile=None,
-                 chirp_exact=None, lane_bins=None):
+                 chirp_exact=None, lane_bins=None, fwd_n2=None):
         self.handle = cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec)
         self.nsub, self.nfft, self.noverlap, self.nchan, self.ndec = \
             nsub, nfft, noverlap, nchan, ndec
@@ -498,6 +512,8 @@ class Plan:
             cdmt_plan_set(self.handle, CDMT_OPT_CHIRP_EXACT, int(chirp_exact))
         if lane_bins is not None:
             cdmt_plan_set(self.handle, CDMT_OPT_LANE_BINS, int(lane_bins))
+        if fwd_n2 is not None:
+            cdmt_plan_set(self.handle, CDMT_OPT_FWD_N2, int(fwd_n2))
         self.input_kind = input_kind
 
     def __del__(self):

@@ -1210,6 +1210,13 @@ void launch_col(const FwdArgs &a, int ci8, int grid, hipStream_t st) {
         fwd_col<P, false><<<grid, 256, 0, st>>>(a);
 }
 
+// The four-step splits the forward kernels are built for: column transforms
+// of n2 in {64, 128, 256}, row transforms of n1 = nfft / n2 in [64, 512].
+bool fwd_split_ok(int nfft, int n2) {
+    return (n2 == 64 || n2 == 128 || n2 == 256) && nfft % n2 == 0 && nfft / n2 >= 64 &&
+           nfft / n2 <= 512;
+}
+
 int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hipStream_t st) {
     const long long nspec = (long long)nblock * p->nsub * p->nfft;
     FwdArgs a;
@@ -1529,6 +1536,12 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
             return CDMT_E_ARG;
         p->lane_bins = value;
         return CDMT_OK;
+    case CDMT_OPT_FWD_N2:
+        if (!fwd_split_ok(p->nfft, value))
+            return CDMT_E_ARG;
+        p->n2 = value;
+        p->n1 = p->nfft / value;
+        return CDMT_OK;
     default:
         return CDMT_E_ARG;
     }
@@ -1545,6 +1558,7 @@ int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
     case CDMT_OPT_DM_TILE: *value = p->dm_tile; return CDMT_OK;
     case CDMT_OPT_CHIRP_EXACT: *value = p->chirp_exact; return CDMT_OK;
     case CDMT_OPT_LANE_BINS: *value = p->lane_bins; return CDMT_OK;
+    case CDMT_OPT_FWD_N2: *value = p->n2; return CDMT_OK;
     default: return CDMT_E_ARG;
     }
 }
@@ -1782,6 +1796,7 @@ struct cdmt_batch_s {
     std::vector<cdmt_beam_t> beams;           // the caller's descriptors
     std::vector<std::vector<double>> dms;     // host copies of the DM lists
     std::vector<size_t> spec_off;             // per beam: spectra in the workspace
+    std::vector<int> fwd_n2;                  // per beam: forward split (0: the plan's)
     size_t dm_off = 0, tab_off = 0, ctr_off = 0;
     char *ws = nullptr;
     int device = 0;
@@ -1911,10 +1926,20 @@ void batch_launch(int recur, const BatchBeam *tab, int count, long long items,
         dm_batch<M, false><<<grid, 256, 0, st>>>(tab, count, items, ctr);
 }
 
+// forward stage of beam b with the batch's split for it
+int batch_forward(cdmt_batch_s *bt, int b, hipStream_t st) {
+    const cdmt_beam_t &B = bt->beams[b];
+    cdmt_plan_s q = *B.plan;
+    if (bt->fwd_n2[b]) {
+        q.n2 = bt->fwd_n2[b];
+        q.n1 = q.nfft / q.n2;
+    }
+    return launch_forward(&q, bt->ws + bt->spec_off[b], B.voltages, B.nblock, st);
+}
+
 int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
     for (size_t b = 0; b < bt->beams.size(); ++b) {
-        const cdmt_beam_t &B = bt->beams[b];
-        const int r = launch_forward(B.plan, bt->ws + bt->spec_off[b], B.voltages, B.nblock, st);
+        const int r = batch_forward(bt, (int)b, st);
         if (r)
             return r;
     }
@@ -1990,6 +2015,7 @@ int cdmt_batch_create(cdmt_batch_t *out, const cdmt_beam_t *beams, int nbeam, vo
         bt->beams[b].dm_list = nullptr;       // read during this call only
     }
     bt->spec_off = off;
+    bt->fwd_n2.assign(nbeam, 0);
     bt->dm_off = dm_off;
     bt->tab_off = tab_off;
     bt->ctr_off = ctr_off;
@@ -2036,6 +2062,24 @@ int cdmt_batch_get(cdmt_batch_t bt, int opt, long long *value) {
     }
 }
 
+int cdmt_batch_beam_set(cdmt_batch_t bt, int beam, int opt, int value) {
+    if (!bt || beam < 0 || beam >= (int)bt->beams.size() || opt != CDMT_BATCH_BEAM_FWD_N2)
+        return CDMT_E_ARG;
+    if (value != 0 && !fwd_split_ok(bt->beams[beam].plan->nfft, value))
+        return CDMT_E_ARG;
+    bt->fwd_n2[beam] = value;
+    bt->dirty = true;
+    return CDMT_OK;
+}
+
+int cdmt_batch_beam_get(cdmt_batch_t bt, int beam, int opt, int *value) {
+    if (!bt || !value || beam < 0 || beam >= (int)bt->beams.size() ||
+        opt != CDMT_BATCH_BEAM_FWD_N2)
+        return CDMT_E_ARG;
+    *value = bt->fwd_n2[beam] ? bt->fwd_n2[beam] : bt->beams[beam].plan->n2;
+    return CDMT_OK;
+}
+
 int cdmt_batch_run(cdmt_batch_t bt, void *hip_stream) {
     if (!bt)
         return CDMT_E_ARG;
@@ -2080,29 +2124,55 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
         (void)hipEventDestroy(e0);
         return CDMT_E_DEVICE;
     }
+    // time reps runs of enqueue() after one warm-up
+    const auto timed = [&](auto enqueue, float *ms) {
+        int rc = enqueue();
+        if (rc)
+            return rc;
+        if (hipEventRecord(e0, st) != hipSuccess)
+            return (int)CDMT_E_DEVICE;
+        for (int i = 0; i < reps && !rc; ++i)
+            rc = enqueue();
+        if (rc)
+            return rc;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return (int)CDMT_E_DEVICE;
+        *ms /= reps;
+        return (int)CDMT_OK;
+    };
+    int r = CDMT_OK;
+    // the forward FFT's radix schedule, beam by beam (each beam's forward
+    // stage is its own launches, so the choices are independent)
+    for (int b = 0; b < (int)bt->beams.size() && !r; ++b) {
+        float fbest = 0.f;
+        int fn2 = 0;
+        for (int n2 = 64; n2 <= 256 && !r; n2 *= 2) {
+            if (!fwd_split_ok(bt->beams[b].plan->nfft, n2))
+                continue;
+            bt->fwd_n2[b] = n2;
+            float ms = 0.f;
+            r = timed([&] { return batch_forward(bt, b, st); }, &ms);
+            if (!r && (fbest == 0.f || ms < fbest)) {
+                fbest = ms;
+                fn2 = n2;
+            }
+        }
+        bt->fwd_n2[b] = fn2;
+    }
+    bt->dirty = true;
     static const int kTiles[] = {4, 8, 16};
     static const int kWg[] = {2, 4};
     float best = 0.f;
-    int bt_tile = 16, bt_wg = 2, r = CDMT_OK;
+    int bt_tile = 16, bt_wg = 2;
     for (int tile : kTiles) {
         for (int wg : kWg) {
             if ((r = cdmt_batch_set(bt, CDMT_BATCH_DM_TILE, tile)) ||
                 (r = cdmt_batch_set(bt, CDMT_BATCH_WG_PER_CU, wg)))
                 break;
-            if ((r = batch_enqueue(bt, st)))                  // warm-up
-                break;
             float ms = 0.f;
-            if (hipEventRecord(e0, st) != hipSuccess) { r = CDMT_E_DEVICE; break; }
-            for (int i = 0; i < reps && !r; ++i)
-                r = batch_enqueue(bt, st);
-            if (r)
+            if ((r = timed([&] { return batch_enqueue(bt, st); }, &ms)))
                 break;
-            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                r = CDMT_E_DEVICE;
-                break;
-            }
-            ms /= reps;
             if (best == 0.f || ms < best) {
                 best = ms;
                 bt_tile = tile;

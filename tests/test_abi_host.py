@@ -94,6 +94,13 @@ def test_options(lib):
         cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_LANE_BINS, 8)
         assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_LANE_BINS) == 8
         assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_LANE_BINS, 4) == cdmt.CDMT_E_ARG
+        # forward split of N_bin = 16384: 2^7 x 2^7 by default; N2 in {64, 128, 256}
+        assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_FWD_N2) == 128
+        for n2 in (64, 256, 128):
+            cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_FWD_N2, n2)
+            assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_FWD_N2) == n2
+        for n2 in (32, 512, 100, 0):
+            assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_FWD_N2, n2) == cdmt.CDMT_E_ARG
         for opt, val, want in ((cdmt.CDMT_OPT_SIGN, 0, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_INPUT, 2, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_DM_TILE, 0, cdmt.CDMT_E_ARG),
@@ -246,6 +253,10 @@ def test_batch_validation(lib):
         assert lib.cdmt_batch_get(None, 0, ctypes.byref(v)) == cdmt.CDMT_E_ARG
         assert lib.cdmt_batch_run(None, None) == cdmt.CDMT_E_ARG
         assert lib.cdmt_batch_run_graph(None, P) == cdmt.CDMT_E_ARG
+        iv = ctypes.c_int()
+        assert lib.cdmt_batch_beam_set(None, 0, cdmt.CDMT_BATCH_BEAM_FWD_N2, 128) == cdmt.CDMT_E_ARG
+        assert lib.cdmt_batch_beam_get(None, 0, cdmt.CDMT_BATCH_BEAM_FWD_N2,
+                                       ctypes.byref(iv)) == cdmt.CDMT_E_ARG
         lib.cdmt_batch_destroy(None)
     finally:
         for p in (p1, p2, p3):

@@ -61,11 +61,11 @@ def _inputs(spec, seed):
     return cfg, v
 
 
-def _plan(hip_lib, spec, dm_tile=None):
+def _plan(hip_lib, spec, dm_tile=None, fwd_n2=None):
     return hip_lib.Plan(spec.nsub, spec.f_centre, synth.SUBBAND_MHZ, spec.nfft, spec.noverlap,
                         spec.nchan, spec.ndec,
                         input_kind=hip_lib.INPUT_CI8 if spec.kind == "ci8" else hip_lib.INPUT_CF32,
-                        chirp_ref=spec.chirp_ref, dm_tile=dm_tile)
+                        chirp_ref=spec.chirp_ref, dm_tile=dm_tile, fwd_n2=fwd_n2)
 
 
 def _setup(hip_lib, torch, specs):
@@ -81,8 +81,8 @@ def _setup(hip_lib, torch, specs):
     return beams, host
 
 
-def _single(hip_lib, sp, x, dm_tile):
-    plan = _plan(hip_lib, sp, dm_tile)
+def _single(hip_lib, sp, x, dm_tile, fwd_n2=None):
+    plan = _plan(hip_lib, sp, dm_tile, fwd_n2)
     return plan.dedisperse(x, sp.nblock, sp.dms)
 
 
@@ -135,17 +135,32 @@ def test_batch_graph_replays_and_autotune(hip_lib):
         stream.synchronize()
         for i, b in enumerate(beams):
             assert torch.equal(b[4], eager[i]), f"replay {rep}, beam {i}"
+    # a per-beam forward split (the other radix schedule of beam 0's N_bin 65536)
+    FN2 = hip_lib.CDMT_BATCH_BEAM_FWD_N2
+    assert batch.beam_get(0, FN2) == 256
+    batch.beam_set(0, FN2, 128)
+    assert batch.beam_get(0, FN2) == 128
+    batch.run_graph(stream)                       # captured again
+    stream.synchronize()
+    ref = _single(hip_lib, specs[0], beams[0][2], None, 128)
+    torch.cuda.synchronize()
+    assert torch.equal(beams[0][4], ref), "beam 0 with the 512 x 128 forward split"
+    with pytest.raises(hip_lib.CdmtError):
+        batch.beam_set(1, FN2, 512)               # not a split of 16384
     best = batch.autotune(stream, reps=1)
     stream.synchronize()
     tile = batch.get(hip_lib.CDMT_BATCH_DM_TILE)
     wg = batch.get(hip_lib.CDMT_BATCH_WG_PER_CU)
-    print(f"autotune: dm tile {tile}, {wg} workgroups per CU, {best:.3f} ms", flush=True)
+    splits = [batch.beam_get(i, FN2) for i in range(len(specs))]
+    print(f"autotune: forward N2 {splits}, dm tile {tile}, {wg} workgroups per CU, "
+          f"{best:.3f} ms", flush=True)
     assert best > 0 and tile in (4, 8, 16) and wg in (2, 4)
-    # after tuning (graph captured again) each beam equals its single run at that tile
+    # after tuning (graph captured again) each beam equals its single run with
+    # the chosen split and tile
     batch.run_graph(stream)
     stream.synchronize()
     for i, (sp, b) in enumerate(zip(specs, beams)):
-        ref = _single(hip_lib, sp, b[2], tile)
+        ref = _single(hip_lib, sp, b[2], tile, splits[i])
         torch.cuda.synchronize()
         assert torch.equal(b[4], ref), f"beam {i} after autotune"
 
@@ -208,7 +223,8 @@ def test_batch_24_beam_workload(hip_lib):
     for i in (0, len(beams) - 1):
         d, nov, nblock = cfgs[i]
         plan = hip_lib.Plan(d.nsub, d.f_centre, synth.SUBBAND_MHZ, d.nfft, nov, d.nchan, d.ndec,
-                            input_kind=hip_lib.INPUT_CI8, dm_tile=tile)
+                            input_kind=hip_lib.INPUT_CI8, dm_tile=tile,
+                            fwd_n2=batch.beam_get(i, hip_lib.CDMT_BATCH_BEAM_FWD_N2))
         ref = plan.dedisperse(beams[i][2], nblock, list(d.dms))
         torch.cuda.synchronize()
         assert torch.equal(ref, beams[i][4]), f"beam {i} differs from its single-beam run"

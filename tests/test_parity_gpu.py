@@ -129,6 +129,28 @@ def test_shapes_parity(hip_lib, case):
     assert e_norm <= TOL and e_max <= TOL
 
 
+SPLITS = [  # nfft, nchan, noverlap, N2 (the non-default forward splits)
+    (8192, 32, 1024, 128), (16384, 16, 2048, 64), (16384, 16, 2048, 256),
+    (32768, 8, 4096, 64), (32768, 8, 4096, 256), (65536, 16, 15360, 128),
+]
+
+
+@pytest.mark.parametrize("case", SPLITS, ids=[f"nfft{c[0]}-N2_{c[3]}" for c in SPLITS])
+def test_forward_splits_parity(hip_lib, case):
+    """Every non-default four-step split of the forward FFT (CDMT_OPT_FWD_N2,
+    the radix schedules the batch autotuner chooses from) against the oracle."""
+    nfft, nchan, nov, n2 = case
+    cfg = oracle.Config(2, 130.0, synth.SUBBAND_MHZ, nfft, nov, nchan, 4)
+    _say(f"forward split case {case}")
+    v = _voltages(cfg, 2, 16.0, 5 + n2, "ci8")
+    dms = [0.0, 7.5, 31.0]
+    ref = oracle.dedisperse(cfg, v, 2, dms)
+    gpu = _run_gpu(hip_lib, cfg, v, 2, dms, "ci8", fwd_n2=n2)
+    e_norm, e_max = _errors(gpu, ref)
+    print(f"split {case}: max_d normwise {e_norm:.3e}, max-abs/max {e_max:.3e}")
+    assert e_norm <= TOL and e_max <= TOL
+
+
 def test_dm_tile_and_repeat_bitwise_identical(hip_lib):
     """With the transfer function evaluated per DM, the result of a DM does
     not depend on how DMs are tiled per workgroup, and repeated runs are
