@@ -850,7 +850,12 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
 //   g_z = forward FFT (e^{-}) of g_y        (adjoint of the e^{+} transform)
 //   dL/dDM = sum Re(conj(g_S') i pi g2 S'), g_S' = unswap(g_z), both pols.
 // One workgroup per (chunk group, DM); FP64 partial sums per workgroup,
-// reduced per DM in a fixed order by dm_grad_sum (deterministic).
+// reduced per DM in a fixed order by dm_grad_sum (deterministic).  Work is
+// ordered (subband block, DM, chunk group within the subband block): the
+// channels of one subband block at one DM are neighbours on one XCD, so the
+// G rows they read ([t][ch], one column each) are shared in its L2, and the
+// block's spectra stay there across its DMs.  a.inner = chunk groups per
+// subband block (1 when a group spans several subbands).
 template <int M>
 __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
                                                   const float *__restrict__ gout,
@@ -866,8 +871,9 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
     __shared__ double red[4];
 
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
-    const int d = lw % a.ndm;
-    const int cg = a.cg0 + lw / a.ndm;
+    const int gin = lw % a.inner, rest = lw / a.inner;
+    const int d = rest % a.ndm;
+    const int cg = a.cg0 + (rest / a.ndm) * a.inner + gin;
     const int t = threadIdx.x;
     const int f = t / T, tt = t % T;
     const int chunk = cg * C + f;
@@ -1394,7 +1400,11 @@ int launch_grad_m(const FusedArgs &a0, const double *dms, int ndm, const float *
             dl.dm[i] = dms[first + i];
         a.ndm = cnt;
         const float *g = gout + (long long)first * a0.ntime_out * a0.nch_out;
-        const long long per = kMaxGroups / cnt;
+        // chunk groups per subband block (the launch order keeps a block's
+        // groups together), and launches cut at multiples of it
+        const int C = 4096 / M;
+        a.inner = a0.nchan >= C ? a0.nchan / C : 1;
+        const long long per = kMaxGroups / cnt / a.inner * a.inner;
         for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
             const long long n = ncg - cg0 < per ? ncg - cg0 : per;
             a.cg0 = (int)cg0;
