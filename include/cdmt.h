@@ -320,11 +320,11 @@ void cdmt_batch_destroy(cdmt_batch_t batch);
  *   ddm        > 0 when ntrial > 1
  *   workspace  device, >= cdmt_incoherent_workspace_size bytes (the
  *              filterbanks transposed to [ndm][nch][ntime] and the delay
- *              table, at most ndm * nch * ceil(ntrial / 16) * 16 int32)
+ *              table, at most ndm * nch * ceil(ntrial / 12) * 12 int32)
  *   out        device float32 [ndm][ntrial][nout]
  * CDMT_E_ARG for bad DMs or steps or a NULL pointer, CDMT_E_WORKSPACE for a
  * short workspace, CDMT_E_SHAPE when nout < 1, ndm exceeds 65535, ntime
- * exceeds 2^31 - 1 or ndm * ceil(nout / 256) * ceil(ntrial / 16) exceeds
+ * exceeds 2^31 - 1 or ndm * ceil(nout / 256) * ceil(ntrial / 12) exceeds
  * 2^31 - 1.  The shape call validates the same arguments and returns nout.
  * Asynchronous on hip_stream; on error nothing is written.
  */

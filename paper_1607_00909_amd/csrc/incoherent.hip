@@ -27,8 +27,9 @@ using cdmt::xcd_remap;
 //                  below kIncSpan, as bytes packed in 8 int32 laid out
 //                  [d][group][ch] (a channel pair is one 64-byte load)
 //   inc_transpose  [d][t][ch] -> [d][ch][t] through LDS, so that the sums
-//                  read each channel's series contiguously (64 x 64 tiles
-//                  moved as float4 where the sizes allow, else 32 x 32)
+//                  read each channel's series contiguously (32-channel x
+//                  256-sample tiles moved as float4 where the sizes allow,
+//                  else 32 x 32)
 //   inc_sum        one wave per (coherent DM, kIncK fine trials, kIncT output
 //                  samples), each lane owning kIncS samples 64 apart (so LDS
 //                  reads of consecutive lanes hit consecutive banks).  Per
@@ -56,7 +57,7 @@ struct IncArgs {
 
 constexpr int kIncS = 4;                      // samples per lane, 64 apart
 constexpr int kIncT = 64 * kIncS;             // output samples per workgroup
-constexpr int kIncK = 16;                     // fine trials per workgroup
+constexpr int kIncK = 12;                     // fine trials per workgroup (<= 16)
 constexpr int kIncSpan = 256;                 // widest delay spread staged in LDS
 
 // (both functions evaluate exactly as written, with no fused multiply-adds,
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
     } else {
         // Channels go in pairs whose trial sums interleave, so that the two
         // windows' LDS reads overlap.  A pair's delays (per channel: the first
-        // delay and 15 byte offsets packed in 4 words, padded to 8 words) are
+        // delay and kIncK - 1 byte offsets packed in words, padded to 8 words) are
         // one 64-byte scalar load, issued two pairs ahead; its windows are
         // loaded one pair ahead, while the current pair's trials are summed.
         // The delays rotate through three arrays, so that none are copied.

@@ -328,7 +328,8 @@ def test_incoherent_validation(lib):
             assert nout == 4 * tblk - int(incoherent.delays(cfg, dmax).max())
         z = ctypes.c_size_t()
         assert lib.cdmt_incoherent_workspace_size(p, 4, 3, 101, ctypes.byref(z)) == cdmt.CDMT_OK
-        assert z.value == 3 * 64 * 4 * tblk * 4 + 3 * 112 * 64 * 4   # transposed copy, delays
+        # transposed copy, then the delay table (101 trials padded to 108 = 9 groups of 12)
+        assert z.value == 3 * 64 * 4 * tblk * 4 + 3 * 108 * 64 * 4
         arr = (ctypes.c_double * 3)(0.5, 10.0, 20.0)
         nout = ctypes.c_longlong()
         shape = lib.cdmt_incoherent_shape
