@@ -269,9 +269,14 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
         const auto fetch = [&](bool real, const float *r, int lo, float (&pf)[kPf]) {
             if (real) {
                 const auto v = view(r, lo);
+                // the lane's byte offset, opaque to the compiler here so that
+                // each load adds its constant in the instruction's offset
+                // field instead of holding kPf offsets in registers
+                int off = 4 * lane;
+                asm volatile("" : "+v"(off));
 #pragma unroll
                 for (int m = 0; m < kPf; ++m)
-                    pf[m] = inc_load(v, 4 * (lane + 64 * m));
+                    pf[m] = inc_load(v, off + 256 * m);
             } else {
 #pragma unroll
                 for (int m = 0; m < kPf; ++m)
