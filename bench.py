@@ -273,13 +273,32 @@ def incoherent_leg(cdmt, torch, plan, w, out, dms, steps: int):
     ev[1].record(stream)
     torch.cuda.synchronize()
     ms = ev[0].elapsed_time(ev[1]) / steps
+    # the same stage fed channel-major filterbanks (what a plan with
+    # CDMT_OPT_OUT_LAYOUT = 1 writes): no transpose inside the call
+    cm_plan = cdmt.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                        out_layout=cdmt.LAYOUT_CHANNEL_MAJOR)
+    fb_cm = fb.transpose(1, 2).contiguous()
+    cm_out = torch.empty_like(iout)
+    cdmt.incoherent(cm_plan, fb_cm, w.nblock, dm_coh, ddm0, ddm, ntrial, out=cm_out,
+                    workspace=iws)
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for _ in range(steps):
+        cdmt.incoherent(cm_plan, fb_cm, w.nblock, dm_coh, ddm0, ddm, ntrial, out=cm_out,
+                        workspace=iws)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms_cm = ev[0].elapsed_time(ev[1]) / steps
+    same = bool(torch.equal(cm_out, iout))
+    del fb_cm, cm_out
     nch = fb.shape[2]
     tsamp = w.nchan * w.ndec / (w.bw * 1e6)
     adds = len(dm_coh) * ntrial * nout * nch
     adds_peak = 256 * 64 * 2.4e9                 # FP32 adds per second, one per lane per clock
     traffic = measured_traffic("inc_sum<false>", PROFILE_INC, ("incoherent.hip", "plan.hpp"))
     del iws, iout
-    return {"ms": round(ms, 3), "coherent_dms": len(dm_coh), "fine_trials": ntrial,
+    return {"ms": round(ms, 3), "ms_channel_major_input": round(ms_cm, 3),
+            "channel_major_identical": same, "coherent_dms": len(dm_coh), "fine_trials": ntrial,
             "nout": nout,
             "trial_seconds_per_s": round(len(dm_coh) * ntrial * nout * tsamp / (ms / 1e3), 1),
             "roofline": {"bound": "alu", "achieved": round(adds / (ms / 1e3) / 1e12, 2),

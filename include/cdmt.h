@@ -57,12 +57,18 @@ enum cdmt_opt {
     CDMT_OPT_LANE_BINS = 6,  /* performance knob of the DM stage: spectral bins held per
                                 GPU lane, 16 (default) or 8 (twice the lanes per channel,
                                 half the registers; used for M_bin = 2048 and 4096)      */
-    CDMT_OPT_FWD_N2 = 7      /* radix schedule of the forward FFT: the four-step split
+    CDMT_OPT_FWD_N2 = 7,     /* radix schedule of the forward FFT: the four-step split
                                 N_bin = N1 * N2 with column transforms of N2 in
                                 {64, 128, 256} and row transforms of N1 = N_bin / N2 in
                                 [64, 512] (CDMT_E_ARG otherwise); default N2 =
                                 2^floor(log2(N_bin) / 2).  Splits give the same spectra
                                 up to FP32 rounding                                     */
+    CDMT_OPT_OUT_LAYOUT = 8  /* filterbank layout of every call on this plan (DM stage,
+                                batches, gradients' dL/dF, incoherent stage input):
+                                0 (default): [DM][time][channel] (Sec. 3's transpose);
+                                1: [DM][channel][time], which the incoherent stage
+                                reads without its own transpose.  Same values either
+                                way, bit for bit                                        */
 };
 
 /*
@@ -140,7 +146,8 @@ int cdmt_forward(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const void 
  *             must be finite with |DM| small enough that the largest phase of
  *             Eq. 1 over the plan stays below 2^29 cycles (CDMT_E_ARG
  *             otherwise; the bound is ~1e7 pc cm^-3 at LOFAR frequencies)
- *   out       device float32 [ndm][ntime_out][nsub*nchan]
+ *   out       device float32 [ndm][ntime_out][nsub*nchan] ([ndm][nsub*nchan]
+ *             [ntime_out] with CDMT_OPT_OUT_LAYOUT = 1)
  * ndm = 0 is a no-op.
  */
 int cdmt_dedisperse_spectra(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nblock,
@@ -163,7 +170,8 @@ int cdmt_dedisperse(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const vo
  *             chirped spectrum S' (through detection, the downsampling sum and
  *             the backward FFT; the complex time series are recomputed, not
  *             stored), pi g2 = d(phase)/dDM of Eq. 1.
- *   grad_out  device float32 [ndm][ntime_out][nchan_out] (layout of the output)
+ *   grad_out  device float32 [ndm][ntime_out][nchan_out] (the plan's output
+ *             layout, CDMT_OPT_OUT_LAYOUT)
  *   dldm      device float64 [ndm]
  *   gws       device, >= cdmt_gradient_workspace_size bytes (FP64 partial
  *             sums, 8 bytes per DM per 4096-bin chunk group)
@@ -182,7 +190,8 @@ int cdmt_dm_gradient(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nbl
  * FFT, swap of halves, segmentation into overlapping blocks), i.e.
  *   grad_v[s][t][p] = dL/dRe x + i dL/dIm x  (stored re, im as float32)
  * for the voltages x that cdmt_forward turned into the spectra in workspace.
- *   grad_out  device float32 [ntime_out][nchan_out]: dL/dF of this DM
+ *   grad_out  device float32 [ntime_out][nchan_out] (the plan's output
+ *             layout): dL/dF of this DM
  *   grad_v    device float32 [nsub][ntime_in][2 pol][re, im] (layout of
  *             complex float32 voltages); overwritten (accumulate = 0) or
  *             added to (accumulate = 1)
@@ -243,7 +252,8 @@ typedef struct {
     const void *voltages;      /* device, as for cdmt_forward                             */
     const double *dm_list;     /* host, ndm finite values, read during create only        */
     int ndm;                   /* >= 1                                                    */
-    float *out;                /* device [ndm][ntime_out][nchan_out] of this beam         */
+    float *out;                /* device [ndm][ntime_out][nchan_out] of this beam (its
+                                  plan's CDMT_OPT_OUT_LAYOUT)                           */
 } cdmt_beam_t;
 
 enum cdmt_batch_opt {
@@ -316,6 +326,8 @@ void cdmt_batch_destroy(cdmt_batch_t batch);
  * delay (lowest channel, largest trial DM), ntime = nblock * tblk.  Sums in
  * FP32 over channels in increasing order.
  *   fb         device float32 [ndm][ntime][nsub*nchan], decreasing frequency
+ *              ([ndm][nsub*nchan][ntime] when the plan's CDMT_OPT_OUT_LAYOUT
+ *              is 1: then no transposed copy is made)
  *   dm_coh     host, ndm values;  every DM_dk must be >= 0
  *   ddm        > 0 when ntrial > 1
  *   workspace  device, >= cdmt_incoherent_workspace_size bytes (the

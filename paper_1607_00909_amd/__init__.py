@@ -23,7 +23,9 @@ CDMT_OK, CDMT_E_ARG, CDMT_E_SHAPE, CDMT_E_WORKSPACE, CDMT_E_DEVICE, CDMT_E_UNSUP
     0, -1, -2, -3, -4, -5
 # enum cdmt_opt
 CDMT_OPT_INPUT, CDMT_OPT_CHIRP_REF, CDMT_OPT_SIGN, CDMT_OPT_PRECISION, CDMT_OPT_DM_TILE, \
-    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS, CDMT_OPT_FWD_N2 = 0, 1, 2, 3, 4, 5, 6, 7
+    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS, CDMT_OPT_FWD_N2, CDMT_OPT_OUT_LAYOUT = \
+    0, 1, 2, 3, 4, 5, 6, 7, 8
+LAYOUT_TIME_MAJOR, LAYOUT_CHANNEL_MAJOR = 0, 1
 INPUT_CF32, INPUT_CI8 = 0, 1
 CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
 
@@ -295,8 +297,7 @@ def _dm_stage_function():
         @staticmethod
         def forward(ctx, dms, plan, nblock, workspace):
             dm_list = [float(v) for v in dms.detach().cpu().tolist()]
-            _, ntout, nch = plan.shape(nblock)
-            out = torch.empty((len(dm_list), ntout, nch), dtype=torch.float32,
+            out = torch.empty(plan.out_shape(len(dm_list), nblock), dtype=torch.float32,
                               device=workspace.device)
             plan.dedisperse_spectra(nblock, dm_list, out, workspace)
             ctx.plan, ctx.nblock, ctx.ws, ctx.dm_list = plan, nblock, workspace, dm_list
@@ -326,8 +327,8 @@ def _dm_stage_function():
         def forward(ctx, x, dms, plan, nblock, workspace):
             dm_list = [float(v) for v in dms.detach().cpu().tolist()]
             plan.forward(x.detach(), nblock, workspace)
-            _, ntout, nch = plan.shape(nblock)
-            out = torch.empty((len(dm_list), ntout, nch), dtype=torch.float32, device=x.device)
+            out = torch.empty(plan.out_shape(len(dm_list), nblock), dtype=torch.float32,
+                              device=x.device)
             plan.dedisperse_spectra(nblock, dm_list, out, workspace)
             ctx.plan, ctx.nblock, ctx.ws, ctx.dm_list = plan, nblock, workspace, dm_list
             ctx.dms_device, ctx.dms_dtype = dms.device, dms.dtype
@@ -442,11 +443,11 @@ class Batch:
         arr = (Beam * len(beams))()
         for i, (plan, nblock, x, dms, out) in enumerate(beams):
             plan._check_voltages(x, nblock)
-            _, ntout, nch = plan.shape(nblock)
+            want = plan.out_shape(len(dms), nblock)
             if (out.dtype != torch.float32 or not out.is_cuda or not out.is_contiguous()
-                    or tuple(out.shape) != (len(dms), ntout, nch)):
+                    or tuple(out.shape) != want):
                 raise ValueError(f"beam {i}: output must be a contiguous float32 "
-                                 f"{(len(dms), ntout, nch)} device tensor")
+                                 f"{want} device tensor")
             d, n = _dm_array(dms)
             arr[i] = Beam(plan.handle, nblock, x.data_ptr(), d, n, out.data_ptr())
             self._keep += [plan, x, out, d]
@@ -499,7 +500,7 @@ class Plan:
 
     def __init__(self, nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec, *,
                  input_kind=INPUT_CF32, chirp_ref=CHIRP_CHANNEL, sign=-1, dm_tile=None,
-                 chirp_exact=None, lane_bins=None, fwd_n2=None):
+                 chirp_exact=None, lane_bins=None, fwd_n2=None, out_layout=None):
         self.handle = cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec)
         self.nsub, self.nfft, self.noverlap, self.nchan, self.ndec = \
             nsub, nfft, noverlap, nchan, ndec
@@ -514,6 +515,8 @@ class Plan:
             cdmt_plan_set(self.handle, CDMT_OPT_LANE_BINS, int(lane_bins))
         if fwd_n2 is not None:
             cdmt_plan_set(self.handle, CDMT_OPT_FWD_N2, int(fwd_n2))
+        if out_layout is not None:
+            cdmt_plan_set(self.handle, CDMT_OPT_OUT_LAYOUT, int(out_layout))
         self.input_kind = input_kind
 
     def __del__(self):
@@ -524,6 +527,13 @@ class Plan:
 
     def shape(self, nblock):
         return cdmt_output_shape(self.handle, nblock)
+
+    def out_shape(self, ndm, nblock):
+        """Filterbank tensor shape for ndm DMs: (ndm, ntime_out, nch) or, with
+        the channel-major layout, (ndm, nch, ntime_out)."""
+        _, ntout, nch = self.shape(nblock)
+        layout = cdmt_plan_get(self.handle, CDMT_OPT_OUT_LAYOUT)
+        return (ndm, nch, ntout) if layout == LAYOUT_CHANNEL_MAJOR else (ndm, ntout, nch)
 
     def workspace(self, nblock, device="cuda"):
         import torch
@@ -549,9 +559,9 @@ class Plan:
         x [nsub][ntime_in][2][2] (float32 or int8)."""
         import torch
         self._check_voltages(x, nblock)
-        _, ntout, nch = self.shape(nblock)
         if out is None:
-            out = torch.empty((len(dms), ntout, nch), dtype=torch.float32, device=x.device)
+            out = torch.empty(self.out_shape(len(dms), nblock), dtype=torch.float32,
+                              device=x.device)
         if workspace is None:
             workspace = self.workspace(nblock, x.device)
         cdmt_dedisperse(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
@@ -579,10 +589,10 @@ def incoherent(plan, fb, nblock, dm_coh, ddm0, ddm, ntrial, out=None, workspace=
     out [ndm][ntrial][nout] float32."""
     import torch
     ndm = len(dm_coh)
-    _, ntout, nch = plan.shape(nblock)
+    want = plan.out_shape(ndm, nblock)
     if (fb.dtype != torch.float32 or not fb.is_cuda or not fb.is_contiguous()
-            or tuple(fb.shape) != (ndm, ntout, nch)):
-        raise ValueError(f"fb must be a contiguous float32 device tensor {(ndm, ntout, nch)}")
+            or tuple(fb.shape) != want):
+        raise ValueError(f"fb must be a contiguous float32 device tensor {want}")
     nout = cdmt_incoherent_shape(plan.handle, nblock, dm_coh, ddm0, ddm, ntrial)
     if out is None:
         out = torch.empty((ndm, ntrial, nout), dtype=torch.float32, device=fb.device)

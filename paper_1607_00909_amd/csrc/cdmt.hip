@@ -220,6 +220,10 @@ struct FusedArgs {
     long long ntime_out;
     int nsub, nchan, n, nchunks, ndm, dm_tile;
     int nd_half, ndec, tblk, nch_out;
+    // filterbank element (t, col) of a DM at t * t_stride + col * col_stride:
+    // (nch_out, 1) time-major [t][ch] (default), (1, ntime_out) channel-major
+    int t_stride;
+    long long col_stride;
     int inner, ndt;         // chunk groups per subband block; DM tiles
     int cg0;                // first chunk group of this launch
     double dm_step;         // DM spacing when the list is an arithmetic progression
@@ -359,7 +363,8 @@ __device__ __forceinline__ void dm_item(const FusedArgs &a, DMS dms, int dt, int
         }
         __syncthreads();
         if (valid) {
-            float *o = a.out + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + col;
+            float *o = a.out + (long long)d * a.ntime_out * a.nch_out +
+                       (long long)b * a.tblk * a.t_stride + col * a.col_stride;
             if (((a.ndec | a.nd_half) & 3) == 0) {
                 // 16-byte LDS reads when the summed runs are 4-float aligned
                 const int n4 = a.ndec >> 2;
@@ -370,7 +375,7 @@ __device__ __forceinline__ void dm_item(const FusedArgs &a, DMS dms, int dt, int
                         const float4 x = p[q];
                         acc += (x.x + x.y) + (x.z + x.w);
                     }
-                    o[(long long)tq * a.nch_out] = acc;
+                    o[(long long)tq * a.t_stride] = acc;
                 }
             } else {
                 for (int tq = tt; tq < a.tblk; tq += T) {
@@ -378,7 +383,7 @@ __device__ __forceinline__ void dm_item(const FusedArgs &a, DMS dms, int dt, int
                     float acc = 0.f;
                     for (int q = 0; q < a.ndec; ++q)
                         acc += p[q];
-                    o[(long long)tq * a.nch_out] = acc;
+                    o[(long long)tq * a.t_stride] = acc;
                 }
             }
         }
@@ -812,7 +817,8 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
         }
         __syncthreads();
         {
-            float *o = a.out + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + colo;
+            float *o = a.out + (long long)d * a.ntime_out * a.nch_out +
+                       (long long)b * a.tblk * a.t_stride + colo * a.col_stride;
             if (((a.ndec | a.nd_half) & 3) == 0) {
                 const int n4 = a.ndec >> 2;
                 for (int tq = t_id; tq < a.tblk; tq += 256) {
@@ -822,7 +828,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
                         const float4 x = p[q];
                         acc += (x.x + x.y) + (x.z + x.w);
                     }
-                    o[(long long)tq * a.nch_out] = acc;
+                    o[(long long)tq * a.t_stride] = acc;
                 }
             } else {
                 for (int tq = t_id; tq < a.tblk; tq += 256) {
@@ -830,7 +836,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_mx(FusedArgs a, DmLis
                     float acc = 0.f;
                     for (int q = 0; q < a.ndec; ++q)
                         acc += p[q];
-                    o[(long long)tq * a.nch_out] = acc;
+                    o[(long long)tq * a.t_stride] = acc;
                 }
             }
         }
@@ -917,13 +923,14 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
     cdmt::wg_fft<M, +1>(v, tt, lds);               // y, sample m = tt + T q
 
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
-    const float *g = gout + ((long long)d * a.ntime_out + (long long)b * a.tblk) * a.nch_out + col;
+    const float *g = gout + (long long)d * a.ntime_out * a.nch_out +
+                     (long long)b * a.tblk * a.t_stride + col * a.col_stride;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int m = tt + T * q;
         float gi = 0.f;
         if (valid && m >= a.nd_half && m < M - a.nd_half)
-            gi = g[(long long)((m - a.nd_half) / a.ndec) * a.nch_out];
+            gi = g[(long long)((m - a.nd_half) / a.ndec) * a.t_stride];
         v[q] = cdmt::pscale(v[q], 2.0f * gi);
     }
     __syncthreads();                               // the first transform's LDS reads are done
@@ -1011,13 +1018,13 @@ __global__ __launch_bounds__(256, 2) void dv_spec(FusedArgs a, double dm,
     cdmt::wg_fft<M, +1>(v, tt, lds);                         // y
 
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
-    const float *g = gout + (long long)b * a.tblk * a.nch_out + col;
+    const float *g = gout + (long long)b * a.tblk * a.t_stride + col * a.col_stride;
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int m = tt + T * q;
         float gi = 0.f;
         if (valid && m >= a.nd_half && m < M - a.nd_half)
-            gi = g[(long long)((m - a.nd_half) / a.ndec) * a.nch_out];
+            gi = g[(long long)((m - a.nd_half) / a.ndec) * a.t_stride];
         v[q] = cdmt::pscale(v[q], 2.0f * gi);
     }
     __syncthreads();
@@ -1351,6 +1358,8 @@ FusedArgs fused_args(const cdmt_plan_s *p, void *ws, int nblock, float *out) {
     a.ndec = p->ndec;
     a.tblk = p->tblk;
     a.nch_out = p->nsub * p->nchan;
+    a.t_stride = p->out_layout ? 1 : a.nch_out;
+    a.col_stride = p->out_layout ? a.ntime_out : 1;
     a.chirp_ref = p->chirp_ref;
     a.sign = (float)p->sign;
     a.f_centre = p->f_centre;
@@ -1552,6 +1561,11 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
         p->n2 = value;
         p->n1 = p->nfft / value;
         return CDMT_OK;
+    case CDMT_OPT_OUT_LAYOUT:
+        if (value != 0 && value != 1)
+            return CDMT_E_ARG;
+        p->out_layout = value;
+        return CDMT_OK;
     default:
         return CDMT_E_ARG;
     }
@@ -1569,6 +1583,7 @@ int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
     case CDMT_OPT_CHIRP_EXACT: *value = p->chirp_exact; return CDMT_OK;
     case CDMT_OPT_LANE_BINS: *value = p->lane_bins; return CDMT_OK;
     case CDMT_OPT_FWD_N2: *value = p->n2; return CDMT_OK;
+    case CDMT_OPT_OUT_LAYOUT: *value = p->out_layout; return CDMT_OK;
     default: return CDMT_E_ARG;
     }
 }

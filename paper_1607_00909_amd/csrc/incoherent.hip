@@ -426,7 +426,9 @@ int cdmt_incoherent_workspace_size(cdmt_plan_t p, int nblock, int ndm, int ntria
         return CDMT_E_ARG;
     const size_t nch = (size_t)p->nsub * p->nchan;
     const size_t ntime = (size_t)nblock * p->tblk;
-    const size_t ft = (size_t)ndm * nch * ntime * sizeof(float);
+    // a transposed copy of the filterbanks unless the plan writes them
+    // channel-major already
+    const size_t ft = p->out_layout ? 0 : (size_t)ndm * nch * ntime * sizeof(float);
     const size_t kpad = ((size_t)ntrial + kIncK - 1) / kIncK * kIncK;
     *bytes = ((ft + 255) & ~(size_t)255) + (size_t)ndm * kpad * nch * sizeof(int);
     return CDMT_OK;
@@ -450,8 +452,9 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
     if ((a.nch + 31) / 32 > 65535 || ndm > 65535 || ndelay > 0x7fffffffLL)
         return CDMT_E_SHAPE;
     hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    float *ft = static_cast<float *>(ws);
-    const size_t ftb = (size_t)ndm * a.nch * a.ntime * sizeof(float);
+    const bool chan_major = p->out_layout == 1;
+    float *ft = chan_major ? nullptr : static_cast<float *>(ws);
+    const size_t ftb = chan_major ? 0 : (size_t)ndm * a.nch * a.ntime * sizeof(float);
     int *D = reinterpret_cast<int *>(static_cast<char *>(ws) + ((ftb + 255) & ~(size_t)255));
     const bool narrow = a.ntrial == 1 || inc_narrow(a);
     for (int first = 0; first < ndm; first += kIncDms) {
@@ -466,16 +469,20 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
         if (hipGetLastError() != hipSuccess)
             return CDMT_E_DEVICE;
     }
-    if (a.nch % 4 == 0 && a.ntime % 4 == 0 && reinterpret_cast<uintptr_t>(fb) % 16 == 0 &&
-        reinterpret_cast<uintptr_t>(ft) % 16 == 0)
-        inc_transpose4<32, 256><<<dim3((unsigned)((a.ntime + 255) / 256),
-                                       (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256, 0,
-                                  s>>>(fb, ft, a.ntime, a.nch);
-    else
-        inc_transpose<<<dim3((unsigned)tiles_t, (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256,
-                        0, s>>>(fb, ft, a.ntime, a.nch);
-    if (hipGetLastError() != hipSuccess)
-        return CDMT_E_DEVICE;
+    if (chan_major) {
+        ft = const_cast<float *>(fb);                 // read as is (the kernels only read it)
+    } else {
+        if (a.nch % 4 == 0 && a.ntime % 4 == 0 && reinterpret_cast<uintptr_t>(fb) % 16 == 0 &&
+            reinterpret_cast<uintptr_t>(ft) % 16 == 0)
+            inc_transpose4<32, 256><<<dim3((unsigned)((a.ntime + 255) / 256),
+                                           (unsigned)((a.nch + 31) / 32), (unsigned)ndm), 256, 0,
+                                      s>>>(fb, ft, a.ntime, a.nch);
+        else
+            inc_transpose<<<dim3((unsigned)tiles_t, (unsigned)((a.nch + 31) / 32),
+                                 (unsigned)ndm), 256, 0, s>>>(fb, ft, a.ntime, a.nch);
+        if (hipGetLastError() != hipSuccess)
+            return CDMT_E_DEVICE;
+    }
     const int ntile = (int)((a.nout + kIncT - 1) / kIncT);
     const int ngroup = a.kpad / kIncK;
     const unsigned grid = (unsigned)((long long)ndm * ntile * ngroup);

@@ -25,5 +25,6 @@ struct cdmt_plan_s {
     int nsub, nfft, noverlap, nchan, ndec;
     double f_centre, bw;
     int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 16, chirp_exact = 0, lane_bins = 16;
+    int out_layout = 0;     // 0: filterbanks [DM][t][ch], 1: [DM][ch][t]
     int m, nd, tblk, n1, n2;
 };

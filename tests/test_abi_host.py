@@ -101,6 +101,10 @@ def test_options(lib):
             assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_FWD_N2) == n2
         for n2 in (32, 512, 100, 0):
             assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_FWD_N2, n2) == cdmt.CDMT_E_ARG
+        assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_OUT_LAYOUT) == 0
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_OUT_LAYOUT, 1)
+        assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_OUT_LAYOUT) == 1
+        assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_OUT_LAYOUT, 2) == cdmt.CDMT_E_ARG
         for opt, val, want in ((cdmt.CDMT_OPT_SIGN, 0, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_INPUT, 2, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_DM_TILE, 0, cdmt.CDMT_E_ARG),
@@ -330,6 +334,12 @@ def test_incoherent_validation(lib):
         assert lib.cdmt_incoherent_workspace_size(p, 4, 3, 101, ctypes.byref(z)) == cdmt.CDMT_OK
         # transposed copy, then the delay table (101 trials padded to 108 = 9 groups of 12)
         assert z.value == 3 * 64 * 4 * tblk * 4 + 3 * 108 * 64 * 4
+        # a channel-major plan's filterbanks are read as they are: the table only
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_OUT_LAYOUT, 1)
+        z1 = ctypes.c_size_t()
+        assert lib.cdmt_incoherent_workspace_size(p, 4, 3, 101, ctypes.byref(z1)) == cdmt.CDMT_OK
+        assert z1.value == 3 * 108 * 64 * 4
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_OUT_LAYOUT, 0)
         arr = (ctypes.c_double * 3)(0.5, 10.0, 20.0)
         nout = ctypes.c_longlong()
         shape = lib.cdmt_incoherent_shape

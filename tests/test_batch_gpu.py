@@ -116,6 +116,30 @@ def test_batch_matches_single_beams_and_oracle(hip_lib):
         assert e <= 1e-5
 
 
+def test_batch_with_a_channel_major_beam(hip_lib):
+    """Beams keep their plan's filterbank layout in a batch: a channel-major
+    beam equals its single-beam run, and the time-major one too."""
+    torch = _torch()
+    print("[gpu-case] batch with a channel-major beam", flush=True)
+    specs = SPECS[:2]
+    beams = []
+    for i, sp in enumerate(specs):
+        cfg, v = _inputs(sp, 400 + i)
+        plan = hip_lib.Plan(sp.nsub, sp.f_centre, synth.SUBBAND_MHZ, sp.nfft, sp.noverlap,
+                            sp.nchan, sp.ndec,
+                            input_kind=hip_lib.INPUT_CI8 if sp.kind == "ci8" else hip_lib.INPUT_CF32,
+                            chirp_ref=sp.chirp_ref, out_layout=1 - i)
+        out = torch.full(plan.out_shape(len(sp.dms), sp.nblock), float("nan"), device="cuda")
+        beams.append((plan, sp.nblock, torch.from_numpy(v).cuda(), sp.dms, out))
+    batch = hip_lib.Batch(beams)
+    batch.run()
+    torch.cuda.synchronize()
+    for plan, nblock, x, dms, out in beams:
+        ref = plan.dedisperse(x, nblock, dms)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+
+
 def test_batch_graph_replays_and_autotune(hip_lib):
     torch = _torch()
     print("[gpu-case] batch graph + autotune", flush=True)

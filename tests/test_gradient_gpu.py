@@ -271,3 +271,42 @@ def test_autograd_voltage_and_dm_gradients(hip_lib):
     torch.cuda.synchronize()
     assert torch.equal(x.grad, gx)
     assert torch.equal(dms.grad, dldm.cpu())
+
+
+def test_gradients_in_the_channel_major_layout(hip_lib):
+    """With CDMT_OPT_OUT_LAYOUT = 1, dL/dF is read [DM][channel][time]: both
+    gradients equal the default layout's, bit for bit, for the transposed G."""
+    torch = _torch()
+    import ctypes
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    nsub, fc, nfft, nov, nchan, ndec, nblock = 3, 130.0, 16384, 4096, 8, 4, 2
+    print("[gpu-case] gradients, channel-major layout", flush=True)
+    cfg = oracle.Config(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec)
+    v = synth.encode_cf32(synth.gaussian_voltages(nsub, cfg.ntime_in(nblock), 1.0, 43))
+    xd = torch.from_numpy(v).cuda()
+    dms = [2.0, 7.7, 19.0]
+    res = []
+    for layout in (0, 1):
+        plan = hip_lib.Plan(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec, chirp_exact=1,
+                            out_layout=layout)
+        ws = plan.workspace(nblock)
+        plan.forward(xd, nblock, ws)
+        _, ntout, nch = plan.shape(nblock)
+        G = torch.from_numpy(np.random.default_rng(14).standard_normal(
+            (len(dms), ntout, nch)).astype(np.float32)).cuda()
+        if layout:
+            G = G.transpose(1, 2).contiguous()
+        n = hip_lib.cdmt_gradient_workspace_size(plan.handle, nblock, len(dms))
+        gws = torch.empty(max(1, n), dtype=torch.uint8, device="cuda")
+        dldm = torch.empty(len(dms), dtype=torch.float64, device="cuda")
+        hip_lib.cdmt_dm_gradient(plan.handle, P(ws), ws.numel(), nblock, dms, P(G), P(gws),
+                                 gws.numel(), P(dldm), None)
+        vsz = hip_lib.cdmt_voltage_gradient_workspace_size(plan.handle, nblock)
+        vws = torch.empty(vsz, dtype=torch.uint8, device="cuda")
+        gx = torch.empty(xd.shape, dtype=torch.float32, device="cuda")
+        hip_lib.cdmt_voltage_gradient(plan.handle, P(ws), ws.numel(), nblock, dms[1], P(G[1]),
+                                      P(vws), vws.numel(), P(gx), 0, None)
+        torch.cuda.synchronize()
+        res.append((dldm.cpu(), gx.cpu()))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.equal(res[0][1], res[1][1])

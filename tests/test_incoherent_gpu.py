@@ -191,3 +191,24 @@ def test_semi_coherent_search_finds_the_pulse(hip_lib):
     assert t == t0 and abs(dm - dm_true) <= 0.02
     assert gpu[at] > 1.5 * max(gpu[0, k0].max(), gpu[1, k0].max())
     assert np.all(np.abs(gpu - ref) <= 1e-5 * np.abs(ref).max())
+
+
+def test_incoherent_reads_channel_major_filterbanks(hip_lib):
+    """A plan with CDMT_OPT_OUT_LAYOUT = 1 has the coherent stage write
+    [DM][channel][time], which the incoherent stage reads without its
+    transpose: the same sums, bit for bit."""
+    torch = _torch()
+    cfg = oracle.Config(4, 140.0, synth.SUBBAND_MHZ, 16384, 4096, 8, 4)
+    nblock = 3
+    print("[gpu-case] incoherent channel-major", flush=True)
+    v = torch.from_numpy(synth.encode_cf32(synth.gaussian_voltages(
+        cfg.nsub, cfg.ntime_in(nblock), 1.0, 51))).cuda()
+    coarse = [1.0, 2.0, 3.0]
+    res = []
+    for layout in (0, 1):
+        plan = hip_lib.Plan(cfg.nsub, cfg.f_centre, cfg.bw, cfg.nfft, cfg.noverlap, cfg.nchan,
+                            cfg.ndec, out_layout=layout)
+        fb = plan.dedisperse(v, nblock, coarse)
+        res.append(hip_lib.incoherent(plan, fb, nblock, coarse, -0.5, 0.01, 101))
+    torch.cuda.synchronize()
+    assert torch.equal(res[0], res[1])

@@ -151,6 +151,38 @@ def test_forward_splits_parity(hip_lib, case):
     assert e_norm <= TOL and e_max <= TOL
 
 
+LAYOUT_CASES = [  # nfft, noverlap, nchan, ndec, mode, options
+    (16384, 4096, 8, 4, oracle.CHANNEL, {}),                                # M 2048, recurrence
+    (16384, 4096, 8, 4, oracle.SUBBAND, {"chirp_exact": 1}),
+    (65536, 15360, 16, 8, oracle.CHANNEL, {"lane_bins": 8}),                # M 4096, 8 bins/lane
+    (65536, 15360, 16, 8, oracle.CHANNEL, {"precision": 2}),                # FP16x3 matrix cores
+    (8192, 1024, 64, 2, oracle.CHANNEL, {}),                                # M 128, 32 chunks/WG
+]
+
+
+@pytest.mark.parametrize("case", LAYOUT_CASES, ids=[f"nfft{c[0]}-{'-'.join(c[5]) or 'fp32'}"
+                                                    for c in LAYOUT_CASES])
+def test_channel_major_layout_is_the_transpose(hip_lib, case):
+    """CDMT_OPT_OUT_LAYOUT = 1 writes the same filterbank [DM][channel][time],
+    bit for bit the transpose of the default layout."""
+    torch = _torch()
+    nfft, nov, nchan, ndec, mode, opts = case
+    cfg = oracle.Config(3, 125.0, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec, chirp_ref=mode)
+    _say(f"layout case {case}")
+    v = torch.from_numpy(_voltages(cfg, 2, 16.0, 71, "ci8")).cuda()
+    dms = list(np.arange(0.0, 36.0, 2.25))
+    outs = []
+    for layout in (0, 1):
+        kw = {k: val for k, val in opts.items() if k != "precision"}
+        plan = _plan(hip_lib, cfg, "ci8", out_layout=layout, **kw)
+        if "precision" in opts:
+            hip_lib.cdmt_plan_set(plan.handle, hip_lib.CDMT_OPT_PRECISION, opts["precision"])
+        outs.append(plan.dedisperse(v, 2, dms))
+    torch.cuda.synchronize()
+    assert outs[1].shape == (len(dms), outs[0].shape[2], outs[0].shape[1])
+    assert torch.equal(outs[1], outs[0].transpose(1, 2).contiguous())
+
+
 def test_dm_tile_and_repeat_bitwise_identical(hip_lib):
     """With the transfer function evaluated per DM, the result of a DM does
     not depend on how DMs are tiled per workgroup, and repeated runs are
