@@ -902,8 +902,12 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
     }
     const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
     const double dm = dl.dm[d];
+    // the chirped spectrum S' is needed again after both transforms: keep the
+    // transfer function (one complex float per bin) and reload the spectrum
+    // then, rather than hold S' (two) through the transforms
     double g2[R];
-    cpair sp[R], v[R];
+    float2 h[R];
+    cpair v[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const double nu = ((double)(tt + T * q) + off) * a.delta;
@@ -916,8 +920,8 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
         sn = __int_as_float(__float_as_int(sn) ^ flip);
         cs = __int_as_float(__float_as_int(cs) ^ flip);
         const cpair r = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
-        sp[q] = cdmt::pmul(r, make_float2(cs, sn));
-        v[q ^ (R / 2)] = sp[q];
+        h[q] = make_float2(cs, sn);
+        v[q ^ (R / 2)] = cdmt::pmul(r, h[q]);
     }
     const cdmt::LdsPad<R> lds{sh + f * STRIDE};
     cdmt::wg_fft<M, +1>(v, tt, lds);               // y, sample m = tt + T q
@@ -940,7 +944,8 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const cpair gz = v[q ^ (R / 2)];           // g_S' of this lane's bin q
-        const cpair x = sp[q];
+        const cpair r = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        const cpair x = cdmt::pmul(r, h[q]);       // S', as before the transforms
         const float tx = gz.y * x.x - gz.x * x.y;  // Re(conj(g) i S'), pol X
         const float ty = gz.w * x.z - gz.z * x.w;  // pol Y
         acc = fma(g2[q], (double)tx + (double)ty, acc);
