@@ -11,7 +11,7 @@ detection, downsampling, transpose) into an FP32 filterbank
 [128][15288][4608] that stays in device memory.
 
 Metric: DM trials x seconds of data processed per second of wall time.
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 
 METRIC = "DM-trials×data-sec per sec (LOFAR-shaped), %HBM peak; mixed vs FP32 plain"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak without packed FP32 instructions (this build emits none):
+# FP32 vector peak without packed FP32 instructions (the library emits none):
 # 256 CUs x 64 lanes per clock x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.  The
 # published 157.3 TFLOP/s counts packed FP32 (two FMAs per lane).
 VALU_FP32_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
@@ -336,7 +336,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 

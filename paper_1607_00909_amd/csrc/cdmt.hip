@@ -1812,7 +1812,7 @@ const char *cdmt_status_string(int status) {
     case CDMT_E_SHAPE: return "shape violates the method's constraints";
     case CDMT_E_WORKSPACE: return "workspace too small";
     case CDMT_E_DEVICE: return "HIP device error";
-    case CDMT_E_UNSUPPORTED: return "configuration not supported by this build";
+    case CDMT_E_UNSUPPORTED: return "configuration not supported by this library";
     default: return "unknown status";
     }
 }
