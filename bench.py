@@ -450,8 +450,8 @@ def main():
                        "forward_algorithmic_GBs": round(fwd_bytes / fwd_avg / 1e9, 1),
                        "forward_frac_of_copy": round(fwd_bytes / fwd_avg / 1e9 / copy_gbs, 4)},
         "realtime_factor": round(w.data_seconds / (elapsed / args.steps), 2),
-        # per-step GPU time (forward + DM stage, HIP events): the median, as the
-        # timing protocol of the method's own measurements reports a central value
+        # per-step GPU time (forward + DM stage, HIP events), median over the
+        # timed steps: robust to one slow step, beside the whole-job mean above
         "step_ms_median": round(sorted(f + u for f, u in zip(fwd_ms, fus_ms))[args.steps // 2], 3),
     }
     outputs = {args.precision: out}
