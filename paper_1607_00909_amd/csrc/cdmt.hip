@@ -1147,7 +1147,7 @@ __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__
         int b = 0;
         while (b + 1 < nbeam && beams[b + 1].item0 <= item)
             ++b;
-        const FusedArgs &a = beams[b].a;
+        const FusedArgs a = beams[b].a;          // a copy: the fields are read once, into SGPRs
         const long long local = item - beams[b].item0;
         const int ci = (int)(local % a.inner);
         const long long rest = local / a.inner;
