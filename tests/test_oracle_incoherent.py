@@ -118,3 +118,16 @@ def test_incoherent_mutants_are_caught(name, monkeypatch):
             except (AssertionError, ValueError, IndexError):
                 caught += 1
     assert caught > 0, f"mutant {name} survived every pin"
+
+
+def test_single_outputs_match_the_full_dedispersion():
+    """incoherent.sample (single outputs, used at full size) gives the same
+    sums as incoherent.dedisperse on every sampled (trial, sample)."""
+    cfg = _cfg(oracle.SUBBAND)
+    fb = np.random.default_rng(9).random((2, 500, cfg.nsub * cfg.nchan))
+    out = incoherent.dedisperse(cfg, fb, [2.0, 6.0], -0.3, 0.05, 13)
+    for d, dm_c in enumerate((2.0, 6.0)):
+        for k in (0, 5, 12):
+            ts = [0, 17, out.shape[2] - 1]
+            got = incoherent.sample(cfg, fb[d], dm_c + (-0.3 + 0.05 * k), ts)
+            assert np.allclose(got, out[d, k, ts], rtol=0, atol=1e-12)
