@@ -310,3 +310,47 @@ def test_gradients_in_the_channel_major_layout(hip_lib):
         res.append((dldm.cpu(), gx.cpu()))
     assert torch.equal(res[0][0], res[1][0])
     assert torch.equal(res[0][1], res[1][1])
+
+
+def test_dm_gradient_at_full_size_on_sampled_pairs(hip_lib):
+    """The benchmark's gradient configuration (288 subbands, N_bin 65536, ~1 s,
+    64 off-grid candidate DMs): dL/dF is non-zero on two sampled (subband,
+    block) pairs only, so the GPU's dL/dDM is the sum of the oracle's gradients
+    of those two pairs."""
+    torch = _torch()
+    import ctypes
+    import math
+    w = synth.LOFAR
+    nblock = math.ceil(synth.SUBBAND_MHZ * 1e6 / (w.nfft - w.noverlap))
+    print("[gpu-case] dm gradient, full size, sampled pairs", flush=True)
+    plan = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                        input_kind=hip_lib.INPUT_CF32, chirp_exact=1)
+    ntin, ntout, nch = plan.shape(nblock)
+    x = synth.device_noise("cf32", w.nsub, ntin, 1.0, 4242, "cuda")
+    ws = plan.workspace(nblock)
+    plan.forward(x, nblock, ws)
+    dms = [5.0 + 0.73 * i for i in range(64)]
+    cfg = oracle.Config(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+    r = np.random.default_rng(15)
+    G = torch.zeros((len(dms), ntout, nch), dtype=torch.float32, device="cuda")
+    total, absum = np.zeros(len(dms)), np.zeros(len(dms))
+    for s, b in ((17, 1), (250, nblock - 1)):
+        cols = [(w.nsub - 1 - s) * w.nchan + (w.nchan - 1 - c) for c in range(w.nchan)]
+        gb = r.standard_normal((len(dms), cfg.tblk, w.nchan)).astype(np.float32)
+        G[:, b * cfg.tblk:(b + 1) * cfg.tblk, cols] = torch.from_numpy(gb).cuda()
+        c1 = oracle.Config(1, cfg.sub_centre(s), cfg.bw, cfg.nfft, cfg.noverlap, cfg.nchan,
+                           cfg.ndec)
+        g = oracle.dm_gradient(c1, x[s:s + 1].cpu().numpy(), 0, b, dms, gb.astype(np.float64))
+        total += g
+        absum += np.abs(g)
+    n = hip_lib.cdmt_gradient_workspace_size(plan.handle, nblock, len(dms))
+    gws = torch.empty(max(1, n), dtype=torch.uint8, device="cuda")
+    dldm = torch.empty(len(dms), dtype=torch.float64, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    hip_lib.cdmt_dm_gradient(plan.handle, P(ws), ws.numel(), nblock, dms, P(G), P(gws),
+                             gws.numel(), P(dldm), None)
+    torch.cuda.synchronize()
+    err = np.abs(dldm.cpu().numpy() - total) / absum
+    print(f"full-size gradient vs oracle (2 pairs x 64 DMs): worst error / sum|terms| "
+          f"{err.max():.2e}", flush=True)
+    assert np.all(err <= 2e-5)
