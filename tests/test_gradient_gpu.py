@@ -350,7 +350,14 @@ def test_dm_gradient_at_full_size_on_sampled_pairs(hip_lib):
     hip_lib.cdmt_dm_gradient(plan.handle, P(ws), ws.numel(), nblock, dms, P(G), P(gws),
                              gws.numel(), P(dldm), None)
     torch.cuda.synchronize()
-    err = np.abs(dldm.cpu().numpy() - total) / absum
-    print(f"full-size gradient vs oracle (2 pairs x 64 DMs): worst error / sum|terms| "
-          f"{err.max():.2e}", flush=True)
-    assert np.all(err <= 2e-5)
+    # With a random dL/dF each DM's gradient is a sum of random-signed terms,
+    # so its size swings from DM to DM while the FP32 rounding error does not
+    # follow it: the error of every DM is measured against the RMS gradient
+    # over the 64 candidates (a DM whose gradient nearly cancels would make
+    # error / |gradient| unbounded at any precision).
+    err = np.abs(dldm.cpu().numpy() - total)
+    scale = float(np.sqrt(np.mean(total ** 2)))
+    print(f"full-size gradient vs oracle (2 pairs x 64 DMs): worst error / RMS gradient "
+          f"{err.max() / scale:.2e}; worst error / sum|pair terms| {(err / absum).max():.2e}",
+          flush=True)
+    assert np.all(err <= 2e-5 * scale)
