@@ -43,6 +43,21 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
     return LIB
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "valu_rate.hip")
+PROBE = os.path.join(HERE, "probe", "valu_rate")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """The VALU issue-rate probe (a stand-alone executable, not part of the library)."""
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    cmd = [hipcc(), *flags, PROBE_SRC, "-o", PROBE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(PROBE + ".tmp", PROBE)
+    return PROBE
+
+
 def stale() -> bool:
     if not os.path.exists(LIB):
         return True
@@ -52,4 +67,5 @@ def stale() -> bool:
 
 if __name__ == "__main__":
     print(build(verbose=True))
+    print(build_probe(verbose=True))
     sys.exit(0)
