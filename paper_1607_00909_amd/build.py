@@ -43,19 +43,19 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
     return LIB
 
 
-PROBE_SRC = os.path.join(HERE, "probe", "valu_rate.hip")
-PROBE = os.path.join(HERE, "probe", "valu_rate")
+PROBES = [os.path.join(HERE, "probe", n) for n in ("valu_rate", "lds_rate")]
 
 
-def build_probe(verbose: bool = False) -> str:
-    """The VALU issue-rate probe (a stand-alone executable, not part of the library)."""
+def build_probe(verbose: bool = False) -> list[str]:
+    """The VALU and LDS rate probes (stand-alone executables, not part of the library)."""
     flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
-    cmd = [hipcc(), *flags, PROBE_SRC, "-o", PROBE + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.check_call(cmd)
-    os.replace(PROBE + ".tmp", PROBE)
-    return PROBE
+    for exe in PROBES:
+        cmd = [hipcc(), *flags, exe + ".hip", "-o", exe + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.check_call(cmd)
+        os.replace(exe + ".tmp", exe)
+    return PROBES
 
 
 def stale() -> bool:
