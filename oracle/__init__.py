@@ -73,7 +73,7 @@ def _load():
             lib.orc_subband_block.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
                                               ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P]
             lib.orc_dm_gradient.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P, ctypes.c_long,
-                                            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P]
+                                            ctypes.c_int, ctypes.c_int, P, ctypes.c_int, P, P, P]
             lib.orc_voltage_gradient.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_int, P,
                                                  ctypes.c_long, ctypes.c_int, ctypes.c_int,
                                                  ctypes.c_double, P, P]
@@ -198,11 +198,14 @@ def subband_block(cfg: Config, x: np.ndarray, s: int, b: int, dms) -> np.ndarray
     return out
 
 
-def dm_gradient(cfg: Config, x: np.ndarray, s: int, b: int, dms, G: np.ndarray) -> np.ndarray:
+def dm_gradient(cfg: Config, x: np.ndarray, s: int, b: int, dms, G: np.ndarray,
+                with_abs: bool = False):
     """d/dDM of L = sum G * F over one subband s and block b, one value per DM
     (F and G as [ndm][tblk][nchan] in increasing channel frequency): the
     adjoint of the per-DM chain of Sec. 3 (chirp of Eq. 1, swap, backward FFT,
-    detection, downsampling), each step's adjoint written out in the C file."""
+    detection, downsampling), each step's adjoint written out in the C file.
+    with_abs: also return, per DM, the sum of the absolute values of the
+    per-bin terms whose sum is the derivative."""
     x = _as_voltages(x)
     dms = np.ascontiguousarray(dms, dtype=np.float64)
     G = np.ascontiguousarray(G, dtype=np.float64)
@@ -210,12 +213,13 @@ def dm_gradient(cfg: Config, x: np.ndarray, s: int, b: int, dms, G: np.ndarray) 
         raise ValueError("G must be [ndm][tblk][nchan]")
     xs = np.ascontiguousarray(x[s])
     out = np.empty(dms.size, dtype=np.float64)
+    absterms = np.empty(dms.size, dtype=np.float64)
     st = _load().orc_dm_gradient(ctypes.byref(cfg.c()), _kind_of(xs), xs.ctypes.data,
                                  xs.shape[0], s, b, dms.ctypes.data, dms.size,
-                                 G.ctypes.data, out.ctypes.data)
+                                 G.ctypes.data, out.ctypes.data, absterms.ctypes.data)
     if st != 0:
         raise ValueError(f"orc_dm_gradient failed ({st})")
-    return out
+    return (out, absterms) if with_abs else out
 
 
 def voltage_gradient(cfg: Config, x: np.ndarray, s: int, nblock: int, dm: float,

@@ -321,9 +321,13 @@ typedef struct {
  *   S'_j = S_j h_j, h_j = exp(sign 2 pi i Phi_j) / N, Phi_j = DM phi_j (Eq. 1
  *   is linear in DM)                        -> dS'_j/dDM = sign 2 pi i phi_j S'_j
  *   dL/dDM = sum_j Re(conj(g_S'_j) dS'_j/dDM), both polarisations.
+ * absterms (may be NULL) receives, per DM, the sum of the absolute values of
+ * those terms, sum_j |Re(conj(g_S'_j) dS'_j/dDM)|: the scale that rounding
+ * errors of a floating-point evaluation of the same sum are measured against.
  */
 int orc_dm_gradient(const orc_cfg *c, int kind, const void *x_sub, long ntime, int s, int b,
-                    const double *dms, int ndm, const double *G, double *dldm)
+                    const double *dms, int ndm, const double *G, double *dldm,
+                    double *absterms)
 {
     if (orc_validate(c))
         return -1;
@@ -359,7 +363,7 @@ int orc_dm_gradient(const orc_cfg *c, int kind, const void *x_sub, long ntime, i
     for (int d = 0; d < ndm; ++d) {
         for (long j = 0; j < n; ++j)
             h[j] = cexp(I * (double)c->sign * 2.0 * ORC_PI * phi[j] * dms[d]) / (double)n;
-        double acc = 0.0;
+        double acc = 0.0, abs_acc = 0.0;
         for (long ch = 0; ch < c->nchan; ++ch) {
             /* dL/dI over the channel's M samples */
             for (long i = 0; i < m; ++i)
@@ -381,11 +385,15 @@ int orc_dm_gradient(const orc_cfg *c, int kind, const void *x_sub, long ntime, i
                     long j = ch * m + (i + m / 2) % m;       /* g_S' at bin j */
                     cplx sp = spec[p * n + j] * h[j];
                     cplx ds = (double)c->sign * 2.0 * ORC_PI * phi[j] * I * sp;
-                    acc += creal(conj(zp[i]) * ds);
+                    const double term = creal(conj(zp[i]) * ds);
+                    acc += term;
+                    abs_acc += fabs(term);
                 }
             }
         }
         dldm[d] = acc;
+        if (absterms)
+            absterms[d] = abs_acc;
     }
     free(spec); free(seg); free(z); free(h); free(phi); free(gi);
     return 0;

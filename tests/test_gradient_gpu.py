@@ -1,14 +1,22 @@
 """GPU DM gradient (cdmt_dm_gradient and the autograd form) against the
 oracle's gradient, and DM refinement of an off-grid pulse by gradient ascent.
 
-Bar: the GPU computes in FP32 with FP64 accumulation; the gradient is a sum
-of many terms of both signs, so the error is stated relative to the sum of
-the absolute per-(subband, block) contributions: |g_gpu - g_ref| <= 2e-5 of
-that sum (measured values are printed)."""
+Bar: dL/dDM is a sum over every bin, channel, polarisation, subband and
+block of the terms t = Re(conj(g_S') dS'/dDM); the GPU forms each term in
+FP32 (two M_bin-point transforms, the transfer function and products) and
+accumulates in FP64.  A rounding-error bound of a sum of terms computed with
+relative error e each is e * sum|t|, so per DM
+    |g_gpu - g_ref| <= c u sum|t|,  u = 2^-24,  c = 2 log2(M_bin) + 8
+(about log2 M roundings per transform, two transforms, plus the transfer
+function and the products), with sum|t| from the oracle (measured values are
+printed)."""
+import math
+
 import numpy as np
 import pytest
 
 import oracle
+from conftest import allow_short_overlap
 from paper_1607_00909_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -21,9 +29,18 @@ def _torch():
     return torch
 
 
+U = 2.0 ** -24
+
+
+def bar(nfft, nchan):
+    """c u of the module's bound for M_bin = nfft / nchan."""
+    return (2 * math.log2(nfft // nchan) + 8) * U
+
+
 def _oracle_gradient(cfg, v, nblock, dms, G):
-    """Sum over every (subband, block) of the oracle's gradient; G in the
-    library's output layout [ndm][ntime_out][nsub*nchan] (decreasing frequency)."""
+    """Sum over every (subband, block) of the oracle's gradient, and the sum
+    of the absolute values of its per-bin terms; G in the library's output
+    layout [ndm][ntime_out][nsub*nchan] (decreasing frequency)."""
     total = np.zeros(len(dms))
     absum = np.zeros(len(dms))
     for s in range(cfg.nsub):
@@ -32,9 +49,9 @@ def _oracle_gradient(cfg, v, nblock, dms, G):
         cols = [(cfg.nsub - 1 - s) * cfg.nchan + (cfg.nchan - 1 - c) for c in range(cfg.nchan)]
         for b in range(nblock):
             gb = G[:, b * cfg.tblk:(b + 1) * cfg.tblk, cols]
-            g = oracle.dm_gradient(c1, v[s:s + 1], 0, b, dms, gb)
+            g, a = oracle.dm_gradient(c1, v[s:s + 1], 0, b, dms, gb, with_abs=True)
             total += g
-            absum += np.abs(g)
+            absum += a
     return total, absum
 
 
@@ -63,6 +80,7 @@ def test_dm_gradient_matches_oracle(hip_lib, case):
     plan = hip_lib.Plan(nsub, fc, synth.SUBBAND_MHZ, nfft, nov, nchan, ndec,
                         input_kind=hip_lib.INPUT_CI8 if kind == "ci8" else hip_lib.INPUT_CF32,
                         chirp_ref=mode, chirp_exact=1)
+    allow_short_overlap(plan, dms)
     ws = plan.workspace(nblock)
     plan.forward(torch.from_numpy(v).cuda(), nblock, ws)
     _, ntout, nch = plan.shape(nblock)
@@ -79,8 +97,9 @@ def test_dm_gradient_matches_oracle(hip_lib, case):
     got = dldm.cpu().numpy()
     ref, absum = _oracle_gradient(cfg, v, nblock, dms, G.astype(np.float64))
     err = np.abs(got - ref) / absum
-    print(f"gradient {got} vs oracle {ref}: error / sum|terms| {err.max():.2e}", flush=True)
-    assert np.all(err <= 2e-5)
+    print(f"gradient {got} vs oracle {ref}: error / sum|terms| {err.max():.2e} "
+          f"(bar {bar(nfft, nchan):.2e})", flush=True)
+    assert np.all(err <= bar(nfft, nchan))
 
 
 def test_autograd_refines_an_off_grid_dm(hip_lib):
@@ -114,8 +133,9 @@ def test_autograd_refines_an_off_grid_dm(hip_lib):
     G = np.zeros((1, nblock * cfg.tblk, nsub * nchan))
     G[0, t0, :] = 1.0
     ref, absum = _oracle_gradient(cfg, v, nblock, [10.0], G)
-    print(f"autograd dL/dDM {g0:.6e}, oracle {ref[0]:.6e}", flush=True)
-    assert abs(g0 - ref[0]) <= 2e-5 * absum[0]
+    print(f"autograd dL/dDM {g0:.6e}, oracle {ref[0]:.6e}, error / sum|terms| "
+          f"{abs(g0 - ref[0]) / absum[0]:.2e}", flush=True)
+    assert abs(g0 - ref[0]) <= bar(nfft, nchan) * absum[0]
 
     dm, L, g = 10.0, L0, g0
     step = 0.5 / abs(g)                          # first move of 0.5 pc cm^-3 at most
@@ -340,9 +360,10 @@ def test_dm_gradient_at_full_size_on_sampled_pairs(hip_lib):
         G[:, b * cfg.tblk:(b + 1) * cfg.tblk, cols] = torch.from_numpy(gb).cuda()
         c1 = oracle.Config(1, cfg.sub_centre(s), cfg.bw, cfg.nfft, cfg.noverlap, cfg.nchan,
                            cfg.ndec)
-        g = oracle.dm_gradient(c1, x[s:s + 1].cpu().numpy(), 0, b, dms, gb.astype(np.float64))
+        g, a = oracle.dm_gradient(c1, x[s:s + 1].cpu().numpy(), 0, b, dms,
+                                  gb.astype(np.float64), with_abs=True)
         total += g
-        absum += np.abs(g)
+        absum += a
     n = hip_lib.cdmt_gradient_workspace_size(plan.handle, nblock, len(dms))
     gws = torch.empty(max(1, n), dtype=torch.uint8, device="cuda")
     dldm = torch.empty(len(dms), dtype=torch.float64, device="cuda")
@@ -350,14 +371,9 @@ def test_dm_gradient_at_full_size_on_sampled_pairs(hip_lib):
     hip_lib.cdmt_dm_gradient(plan.handle, P(ws), ws.numel(), nblock, dms, P(G), P(gws),
                              gws.numel(), P(dldm), None)
     torch.cuda.synchronize()
-    # With a random dL/dF each DM's gradient is a sum of random-signed terms,
-    # so its size swings from DM to DM while the FP32 rounding error does not
-    # follow it: the error of every DM is measured against the RMS gradient
-    # over the 64 candidates (a DM whose gradient nearly cancels would make
-    # error / |gradient| unbounded at any precision).
+    # each DM's gradient is a sum of random-signed terms that can nearly
+    # cancel: the error is bounded by the terms' absolute sum (module bar)
     err = np.abs(dldm.cpu().numpy() - total)
-    scale = float(np.sqrt(np.mean(total ** 2)))
-    print(f"full-size gradient vs oracle (2 pairs x 64 DMs): worst error / RMS gradient "
-          f"{err.max() / scale:.2e}; worst error / sum|pair terms| {(err / absum).max():.2e}",
-          flush=True)
-    assert np.all(err <= 2e-5 * scale)
+    print(f"full-size gradient vs oracle (2 pairs x 64 DMs): worst error / sum|terms| "
+          f"{(err / absum).max():.2e} (bar {bar(w.nfft, w.nchan):.2e})", flush=True)
+    assert np.all(err <= bar(w.nfft, w.nchan) * absum)

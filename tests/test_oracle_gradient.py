@@ -132,3 +132,26 @@ def test_voltage_gradient_euler_identity():
         lhs = float(np.real(np.conj(gx) * x[s]).sum())
         L = _block_loss(cfg, x, s, nblock, dm, G)
         assert abs(lhs - 2 * L) <= 1e-9 * np.abs(G).sum() * np.abs(x[s]).max() ** 2
+
+
+def test_absolute_term_sum_bounds_the_gradient():
+    """The per-DM sum of |per-bin term| (the scale GPU rounding errors are
+    measured against) is at least |dL/dDM| (triangle inequality), scales as
+    |G| (doubling or negating G), vanishes with G, and grows with the number
+    of terms: a dL/dF on one output sample sums fewer terms than on all."""
+    cfg = _cfg(oracle.CHANNEL)
+    x = synth.gaussian_voltages(cfg.nsub, cfg.ntime_in(2), 1.0, 12)
+    G = np.random.default_rng(4).standard_normal((3, cfg.tblk, cfg.nchan))
+    dms = [2.0, 10.0, 33.0]
+    g, a = oracle.dm_gradient(cfg, x, 1, 1, dms, G, with_abs=True)
+    assert np.all(a >= np.abs(g)) and np.all(a > 0)
+    assert np.all(a > 10 * np.abs(g))          # random-signed terms mostly cancel
+    g2, a2 = oracle.dm_gradient(cfg, x, 1, 1, dms, -2.0 * G, with_abs=True)
+    np.testing.assert_allclose(g2, -2.0 * g, rtol=1e-12)
+    np.testing.assert_allclose(a2, 2.0 * a, rtol=1e-12)
+    g0, a0 = oracle.dm_gradient(cfg, x, 1, 1, dms, 0.0 * G, with_abs=True)
+    assert np.all(g0 == 0.0) and np.all(a0 == 0.0)
+    one = np.zeros_like(G)
+    one[:, 5, 2] = G[:, 5, 2]
+    _, a1 = oracle.dm_gradient(cfg, x, 1, 1, dms, one, with_abs=True)
+    assert np.all(a1 < a)

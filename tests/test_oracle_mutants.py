@@ -44,8 +44,8 @@ GRAD_MUTANTS = [
      "cplx ds = -(double)c->sign * 2.0"),
     ("gradient: upstream gradient without the unpad offset",
      "gi[nd / 2 + t * c->ndec + q] = G[", "gi[t * c->ndec + q] = G["),
-    ("gradient: imaginary part taken", "acc += creal(conj(zp[i]) * ds);",
-     "acc += cimag(conj(zp[i]) * ds);"),
+    ("gradient: imaginary part taken", "const double term = creal(conj(zp[i]) * ds);",
+     "const double term = cimag(conj(zp[i]) * ds);"),
     ("gradient: channel swap not inverted", "long j = ch * m + (i + m / 2) % m;       /* g_S' at bin j */",
      "long j = ch * m + i;"),
     ("gradient: one polarisation", "cplx *zp = z + p * m;", "cplx *zp = z + p * m; if (p) continue;"),
