@@ -63,12 +63,17 @@ enum cdmt_opt {
                                 [64, 512] (CDMT_E_ARG otherwise); default N2 =
                                 2^floor(log2(N_bin) / 2).  Splits give the same spectra
                                 up to FP32 rounding                                     */
-    CDMT_OPT_OUT_LAYOUT = 8  /* filterbank layout of every call on this plan (DM stage,
+    CDMT_OPT_OUT_LAYOUT = 8, /* filterbank layout of every call on this plan (DM stage,
                                 batches, gradients' dL/dF, incoherent stage input):
                                 0 (default): [DM][time][channel] (Sec. 3's transpose);
                                 1: [DM][channel][time], which the incoherent stage
                                 reads without its own transpose.  Same values either
                                 way, bit for bit                                        */
+    CDMT_OPT_DM_CHECK = 9    /* 1 (default): every call that takes DMs rejects, with
+                                CDMT_E_SHAPE, any |DM| above cdmt_dm_limit (its Eq. 2
+                                sweep is longer than the overlap, so wrap-around of the
+                                circular convolution would reach the kept samples,
+                                Sec. 2); 0: no such check (a deliberately short overlap) */
 };
 
 /*
@@ -79,7 +84,7 @@ enum cdmt_opt {
  * is centred on f_centre + (s - (n_s-1)/2) * bw.
  *
  *   nsub       n_s >= 1
- *   nfft       N_bin, power of two in [2^12, 2^17] (other powers of two:
+ *   nfft       N_bin, power of two in [2^10, 2^17] (other powers of two:
  *              CDMT_E_UNSUPPORTED)
  *   noverlap   n_d * n_c subband samples; multiple of 2*nchan, < nfft
  *              (Sec. 2: sections overlap by n_d n_c samples, n_d/2 channel
@@ -110,6 +115,15 @@ int cdmt_noverlap_for(double f_lo_mhz, double bw_sub_mhz, double dm_max, int nch
                       int chirp_ref, int *noverlap_out);
 
 /*
+ * The inverse of cdmt_noverlap_for for a plan: the largest |DM| (pc cm^-3)
+ * whose Eq. 2 sweep, in subband samples r t_d with r = bw_sub in samples per
+ * second, fits in the plan's noverlap (Sec. 2: sections overlap by at least
+ * n_d n_c samples, t_d over the lowest channel, or over the lowest subband
+ * when CDMT_OPT_CHIRP_REF = 1).  Writes *dm_max; CDMT_E_ARG for NULL.
+ */
+int cdmt_dm_limit(cdmt_plan_t plan, double *dm_max);
+
+/*
  * Shapes for nblock blocks (Sec. 3, the block loop of Alg. 1):
  *   ntime_in  = nblock*(nfft - noverlap) + noverlap input samples per subband
  *   ntime_out = nblock*(M_bin - n_d)/ndec filterbank samples
@@ -121,7 +135,8 @@ int cdmt_output_shape(cdmt_plan_t plan, int nblock, long long *ntime_in, long lo
                       int *nchan_out);
 
 /* Device workspace in bytes for nblock blocks (spectra of both polarisations
- * plus the four-step intermediate). */
+ * plus the four-step intermediate).  It does not depend on the number of DM
+ * trials: the DM list reaches the kernels by value, so no ndm_max argument. */
 int cdmt_workspace_size(cdmt_plan_t plan, int nblock, size_t *bytes);
 
 /*
@@ -145,7 +160,9 @@ int cdmt_forward(cdmt_plan_t plan, void *workspace, size_t ws_bytes, const void 
  *   dm_list   host, ndm values in pc cm^-3, read during the call only; each
  *             must be finite with |DM| small enough that the largest phase of
  *             Eq. 1 over the plan stays below 2^29 cycles (CDMT_E_ARG
- *             otherwise; the bound is ~1e7 pc cm^-3 at LOFAR frequencies)
+ *             otherwise; the bound is ~1e7 pc cm^-3 at LOFAR frequencies) and,
+ *             unless CDMT_OPT_DM_CHECK = 0, |DM| <= cdmt_dm_limit (CDMT_E_SHAPE
+ *             otherwise).  The same rules hold for every call taking DMs.
  *   out       device float32 [ndm][ntime_out][nsub*nchan] ([ndm][nsub*nchan]
  *             [ntime_out] with CDMT_OPT_OUT_LAYOUT = 1)
  * ndm = 0 is a no-op.
@@ -250,7 +267,9 @@ typedef struct {
     cdmt_plan_t plan;          /* the beam's plan (used during create and runs)           */
     int nblock;                /* blocks of this beam, >= 1                               */
     const void *voltages;      /* device, as for cdmt_forward                             */
-    const double *dm_list;     /* host, ndm finite values, read during create only        */
+    const double *dm_list;     /* host, ndm values, read during create only; checked
+                                  against the beam's plan as by cdmt_dedisperse (phase
+                                  bound, and cdmt_dm_limit unless CDMT_OPT_DM_CHECK = 0) */
     int ndm;                   /* >= 1                                                    */
     float *out;                /* device [ndm][ntime_out][nchan_out] of this beam (its
                                   plan's CDMT_OPT_OUT_LAYOUT)                           */

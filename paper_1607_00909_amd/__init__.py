@@ -23,14 +23,14 @@ CDMT_OK, CDMT_E_ARG, CDMT_E_SHAPE, CDMT_E_WORKSPACE, CDMT_E_DEVICE, CDMT_E_UNSUP
     0, -1, -2, -3, -4, -5
 # enum cdmt_opt
 CDMT_OPT_INPUT, CDMT_OPT_CHIRP_REF, CDMT_OPT_SIGN, CDMT_OPT_PRECISION, CDMT_OPT_DM_TILE, \
-    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS, CDMT_OPT_FWD_N2, CDMT_OPT_OUT_LAYOUT = \
-    0, 1, 2, 3, 4, 5, 6, 7, 8
+    CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS, CDMT_OPT_FWD_N2, CDMT_OPT_OUT_LAYOUT, \
+    CDMT_OPT_DM_CHECK = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
 LAYOUT_TIME_MAJOR, LAYOUT_CHANNEL_MAJOR = 0, 1
 INPUT_CF32, INPUT_CI8 = 0, 1
 CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
 
 # every symbol include/cdmt.h declares
-EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for",
+EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for", "cdmt_dm_limit",
            "cdmt_output_shape", "cdmt_workspace_size", "cdmt_forward",
            "cdmt_dedisperse_spectra", "cdmt_dedisperse", "cdmt_destroy", "cdmt_status_string",
            "cdmt_redigitise_workspace_size", "cdmt_redigitise",
@@ -82,6 +82,7 @@ def load():
         lib.cdmt_plan_set.argtypes = [P, I, I]
         lib.cdmt_plan_get.argtypes = [P, I, ctypes.POINTER(I)]
         lib.cdmt_noverlap_for.argtypes = [D, D, D, I, I, I, ctypes.POINTER(I)]
+        lib.cdmt_dm_limit.argtypes = [P, ctypes.POINTER(D)]
         lib.cdmt_output_shape.argtypes = [P, I, ctypes.POINTER(LL), ctypes.POINTER(LL),
                                           ctypes.POINTER(I)]
         lib.cdmt_workspace_size.argtypes = [P, I, ctypes.POINTER(Z)]
@@ -157,6 +158,12 @@ def cdmt_noverlap_for(f_lo_mhz, bw_sub_mhz, dm_max, nchan, ndec, chirp_ref=CHIRP
     return v.value
 
 
+def cdmt_dm_limit(plan) -> float:
+    v = ctypes.c_double()
+    _check(load().cdmt_dm_limit(plan, ctypes.byref(v)), "cdmt_dm_limit")
+    return v.value
+
+
 def cdmt_output_shape(plan, nblock):
     a, b, c = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
     _check(load().cdmt_output_shape(plan, nblock, ctypes.byref(a), ctypes.byref(b),
@@ -175,7 +182,30 @@ def _dm_array(dms):
     return (ctypes.c_double * max(1, len(dms)))(*dms), len(dms)
 
 
+# Spectra generation per workspace (keyed by its device address): bumped by
+# every call that rewrites the spectra, so that a backward pass can tell
+# whether the spectra its forward pass used are still in the workspace.
+_ws_generation: dict = {}
+
+
+def _ptr(v) -> int:
+    return int(v.value if isinstance(v, ctypes.c_void_p) else v or 0)
+
+
+def _bump(workspace) -> None:
+    k = _ptr(workspace)
+    _ws_generation[k] = _ws_generation.get(k, 0) + 1
+
+
+def workspace_generation(workspace) -> int:
+    """How many times the spectra in this workspace (tensor or address) have
+    been rewritten through this binding."""
+    return _ws_generation.get(_ptr(workspace.data_ptr() if hasattr(workspace, "data_ptr")
+                                   else workspace), 0)
+
+
 def cdmt_forward(plan, workspace, ws_bytes, voltages, nblock, stream) -> None:
+    _bump(workspace)
     _check(load().cdmt_forward(plan, workspace, ws_bytes, voltages, nblock, stream),
            "cdmt_forward")
 
@@ -188,6 +218,7 @@ def cdmt_dedisperse_spectra(plan, workspace, ws_bytes, nblock, dms, out, stream)
 
 def cdmt_dedisperse(plan, workspace, ws_bytes, voltages, nblock, dms, out, stream) -> None:
     arr, n = _dm_array(dms)
+    _bump(workspace)
     _check(load().cdmt_dedisperse(plan, workspace, ws_bytes, voltages, nblock, arr, n, out,
                                   stream), "cdmt_dedisperse")
 
@@ -285,6 +316,27 @@ def cdmt_incoherent(plan, nblock, fb, dm_coh, ddm0, ddm, ntrial, workspace, ws_b
                                   workspace, ws_bytes, out, stream), "cdmt_incoherent")
 
 
+_N_OPTIONS = 10
+
+
+def _snapshot(plan, workspace):
+    """What a backward pass depends on besides its inputs: the spectra in the
+    workspace (their generation) and every plan option."""
+    return (workspace_generation(workspace),
+            tuple(cdmt_plan_get(plan.handle, o) for o in range(_N_OPTIONS)))
+
+
+def _check_snapshot(ctx) -> None:
+    gen, opts = _snapshot(ctx.plan, ctx.ws)
+    if gen != ctx.state[0]:
+        raise RuntimeError("the workspace's spectra were rewritten (another forward or "
+                           "dedisperse call on it) after this graph's forward pass; run "
+                           "backward first or give each forward pass its own workspace")
+    if opts != ctx.state[1]:
+        raise RuntimeError("a plan option changed between this graph's forward and "
+                           "backward passes")
+
+
 def _dm_stage_function():
     import torch
 
@@ -302,10 +354,12 @@ def _dm_stage_function():
             plan.dedisperse_spectra(nblock, dm_list, out, workspace)
             ctx.plan, ctx.nblock, ctx.ws, ctx.dm_list = plan, nblock, workspace, dm_list
             ctx.dms_device, ctx.dms_dtype = dms.device, dms.dtype
+            ctx.state = _snapshot(plan, workspace)
             return out
 
         @staticmethod
         def backward(ctx, grad_out):
+            _check_snapshot(ctx)
             g = grad_out.detach().to(torch.float32).contiguous()
             n = len(ctx.dm_list)
             dldm = torch.empty(n, dtype=torch.float64, device=g.device)
@@ -333,10 +387,12 @@ def _dm_stage_function():
             ctx.plan, ctx.nblock, ctx.ws, ctx.dm_list = plan, nblock, workspace, dm_list
             ctx.dms_device, ctx.dms_dtype = dms.device, dms.dtype
             ctx.x_shape = x.shape
+            ctx.state = _snapshot(plan, workspace)
             return out
 
         @staticmethod
         def backward(ctx, grad_out):
+            _check_snapshot(ctx)
             g = grad_out.detach().to(torch.float32).contiguous()
             plan, nblock, ws = ctx.plan, ctx.nblock, ctx.ws
             stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -500,7 +556,8 @@ class Plan:
 
     def __init__(self, nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec, *,
                  input_kind=INPUT_CF32, chirp_ref=CHIRP_CHANNEL, sign=-1, dm_tile=None,
-                 chirp_exact=None, lane_bins=None, fwd_n2=None, out_layout=None):
+                 chirp_exact=None, lane_bins=None, fwd_n2=None, out_layout=None,
+                 dm_check=None):
         self.handle = cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec)
         self.nsub, self.nfft, self.noverlap, self.nchan, self.ndec = \
             nsub, nfft, noverlap, nchan, ndec
@@ -517,6 +574,8 @@ class Plan:
             cdmt_plan_set(self.handle, CDMT_OPT_FWD_N2, int(fwd_n2))
         if out_layout is not None:
             cdmt_plan_set(self.handle, CDMT_OPT_OUT_LAYOUT, int(out_layout))
+        if dm_check is not None:
+            cdmt_plan_set(self.handle, CDMT_OPT_DM_CHECK, int(dm_check))
         self.input_kind = input_kind
 
     def __del__(self):
@@ -534,6 +593,32 @@ class Plan:
         _, ntout, nch = self.shape(nblock)
         layout = cdmt_plan_get(self.handle, CDMT_OPT_OUT_LAYOUT)
         return (ndm, nch, ntout) if layout == LAYOUT_CHANNEL_MAJOR else (ndm, ntout, nch)
+
+    def dm_limit(self) -> float:
+        """Largest |DM| the plan's overlap supports (Eq. 2)."""
+        return cdmt_dm_limit(self.handle)
+
+    def _check_out(self, out, ndm, nblock, device):
+        """The C call takes no output size: require exactly the filterbank
+        tensor it writes, before any launch."""
+        import torch
+        want = self.out_shape(ndm, nblock)
+        if (not isinstance(out, torch.Tensor) or out.dtype != torch.float32
+                or not out.is_contiguous() or tuple(out.shape) != want):
+            raise ValueError(f"out must be a contiguous float32 tensor of shape {want}")
+        if not out.is_cuda or (device is not None and out.device != torch.device(device)):
+            raise ValueError(f"out must be on the device of the workspace ({device})")
+
+    @staticmethod
+    def _check_workspace(workspace):
+        """A contiguous byte tensor on the device (its size is checked by
+        the library, which reports CDMT_E_WORKSPACE)."""
+        import torch
+        if (not isinstance(workspace, torch.Tensor) or workspace.element_size() != 1
+                or not workspace.is_contiguous()):
+            raise ValueError("workspace must be a contiguous byte tensor")
+        if not workspace.is_cuda:
+            raise ValueError("workspace must be a device tensor")
 
     def workspace(self, nblock, device="cuda"):
         import torch
@@ -564,6 +649,8 @@ class Plan:
                               device=x.device)
         if workspace is None:
             workspace = self.workspace(nblock, x.device)
+        self._check_workspace(workspace)
+        self._check_out(out, len(dms), nblock, workspace.device)
         cdmt_dedisperse(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                         ctypes.c_void_p(x.data_ptr()), nblock, dms,
                         ctypes.c_void_p(out.data_ptr()), self._stream(stream))
@@ -571,10 +658,14 @@ class Plan:
 
     def forward(self, x, nblock, workspace, stream=None):
         self._check_voltages(x, nblock)
+        self._check_workspace(workspace)
         cdmt_forward(self.handle, ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                      ctypes.c_void_p(x.data_ptr()), nblock, self._stream(stream))
 
     def dedisperse_spectra(self, nblock, dms, out, workspace, stream=None):
+        self._check_out(out, len(dms), nblock,
+                        workspace.device if hasattr(workspace, "device") else None)
+        self._check_workspace(workspace)
         cdmt_dedisperse_spectra(self.handle, ctypes.c_void_p(workspace.data_ptr()),
                                 workspace.numel(), nblock, dms, ctypes.c_void_p(out.data_ptr()),
                                 self._stream(stream))
@@ -615,6 +706,6 @@ def dm_seconds(nblock: int, nfft: int, noverlap: int, bw_mhz: float) -> float:
 
 
 __all__ = [n for n in dir() if n.startswith("cdmt_")] + ["Plan", "load", "CdmtError",
-                                                          "dm_seconds", "redigitise", "Batch",
+                                                          "dm_seconds", "redigitise", "Batch", "workspace_generation",
                                                           "Beam", "dedisperse_dm", "dedisperse",
                                                           "incoherent", "EXPORTS"]

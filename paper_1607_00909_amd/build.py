@@ -10,8 +10,10 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("cdmt.hip", "redigit.hip", "incoherent.hip")]
+SRCS = [os.path.join(HERE, "csrc", f)
+        for f in ("cdmt.hip", "redigit.hip", "incoherent.hip", "plan.cpp")]
 DEPS = [*SRCS, os.path.join(HERE, "csrc", "fft_core.hpp"), os.path.join(HERE, "csrc", "plan.hpp"),
+        os.path.join(HERE, "csrc", "xcd.hpp"),
         os.path.join(ROOT, "include", "cdmt.h")]
 LIB = os.path.join(HERE, "libcdmt.so")
 ARCH = os.environ.get("CDMT_OFFLOAD_ARCH", "gfx950")
@@ -43,21 +45,6 @@ def build(verbose: bool = False, save_temps: str | None = None) -> str:
     return LIB
 
 
-PROBES = [os.path.join(HERE, "probe", n) for n in ("valu_rate", "lds_rate")]
-
-
-def build_probe(verbose: bool = False) -> list[str]:
-    """The VALU and LDS rate probes (stand-alone executables, not part of the library)."""
-    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
-    for exe in PROBES:
-        cmd = [hipcc(), *flags, exe + ".hip", "-o", exe + ".tmp"]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
-        os.replace(exe + ".tmp", exe)
-    return PROBES
-
-
 def stale() -> bool:
     if not os.path.exists(LIB):
         return True
@@ -67,5 +54,4 @@ def stale() -> bool:
 
 if __name__ == "__main__":
     print(build(verbose=True))
-    print(build_probe(verbose=True))
     sys.exit(0)

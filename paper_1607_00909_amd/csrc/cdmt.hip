@@ -34,12 +34,14 @@
 #include "../../include/cdmt.h"
 #include "fft_core.hpp"
 #include "plan.hpp"
+#include "xcd.hpp"
 
 using cdmt::cpair;
 
 namespace {
 
 using cdmt::kKdm;
+using namespace cdmt;
 
 constexpr int kMaxDmPerLaunch = 256;
 constexpr int kTwiddleEntries = 1 << 18;   // sizes 1 .. 2^17, table P at [P, 2P)
@@ -147,6 +149,49 @@ __global__ __launch_bounds__(256) void fwd_row(FwdArgs a) {
         const int k = g * C + f2 + a.n2 * k1;
         const int j = (k + half) & (a.n - 1);     // swap halves per subband
         spec[j] = cdmt::pscale(rd.load(k1), a.inv_n);
+    }
+}
+
+// Forward FFT in one pass for N_bin = P <= 2048: C = 4096/P transforms per
+// workgroup, one per (block, subband), lanes along the transform so that the
+// loads are contiguous in time; the swap of halves and 1/N_bin are folded
+// into the store as in fwd_row.
+template <int P, bool CI8>
+__global__ __launch_bounds__(256) void fwd_one(FwdArgs a) {
+    constexpr int T = P / 16, C = 4096 / P;
+    constexpr int STRIDE = P + P / 16 + 1;
+    __shared__ cpair sh[C * STRIDE];
+    const int t = threadIdx.x, f = t / T, tt = t % T;
+    const long long bs = (long long)blockIdx.x * C + f;     // block * nsub + subband
+    const bool valid = bs < (long long)a.nblock * a.nsub;
+    const int s = valid ? (int)(bs % a.nsub) : 0;
+    const int b = valid ? (int)(bs / a.nsub) : 0;
+    const long long first = (long long)s * a.ntime_in + (long long)b * a.step + tt;
+
+    cpair v[16];
+    if constexpr (CI8) {
+        const int *x = reinterpret_cast<const int *>(a.x) + first;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int w = valid ? x[T * q] : 0;
+            v[q] = make_float4((float)(int8_t)w, (float)(int8_t)(w >> 8),
+                               (float)(int8_t)(w >> 16), (float)(int8_t)(w >> 24));
+        }
+    } else {
+        const float4 *x = reinterpret_cast<const float4 *>(a.x) + first;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = valid ? x[T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    cdmt::LdsPadded lds{sh + f * STRIDE};
+    cdmt::wg_fft<P, -1, 16>(v, tt, lds);
+    if (valid) {
+        cpair *spec = a.spec + bs * P;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int k = tt + T * q;
+            spec[(k + P / 2) & (P - 1)] = cdmt::pscale(v[q], a.inv_n);   // swap halves
+        }
     }
 }
 
@@ -1207,13 +1252,6 @@ int ensure_twiddles() {
     return CDMT_OK;
 }
 
-bool is_pow2(long long v) { return v > 0 && (v & (v - 1)) == 0; }
-int ilog2(long long v) {
-    int l = 0;
-    while ((1LL << l) < v)
-        ++l;
-    return l;
-}
 
 }  // namespace
 
@@ -1228,12 +1266,6 @@ void launch_col(const FwdArgs &a, int ci8, int grid, hipStream_t st) {
         fwd_col<P, false><<<grid, 256, 0, st>>>(a);
 }
 
-// The four-step splits the forward kernels are built for: column transforms
-// of n2 in {64, 128, 256}, row transforms of n1 = nfft / n2 in [64, 512].
-bool fwd_split_ok(int nfft, int n2) {
-    return (n2 == 64 || n2 == 128 || n2 == 256) && nfft % n2 == 0 && nfft / n2 >= 64 &&
-           nfft / n2 <= 512;
-}
 
 int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hipStream_t st) {
     const long long nspec = (long long)nblock * p->nsub * p->nfft;
@@ -1251,6 +1283,22 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
     a.inv_n = 1.0f / (float)p->nfft;
 
     const long long bsn = (long long)nblock * p->nsub;
+    if (p->nfft <= 2048) {
+        const int C = 4096 / p->nfft;
+        const long long grid = (bsn + C - 1) / C;
+        if (grid * 256 > 0xffffffffLL)
+            return CDMT_E_SHAPE;
+        const bool ci8 = p->input_kind != 0;
+        if (p->nfft == 1024)
+            ci8 ? fwd_one<1024, true><<<(int)grid, 256, 0, st>>>(a)
+                : fwd_one<1024, false><<<(int)grid, 256, 0, st>>>(a);
+        else if (p->nfft == 2048)
+            ci8 ? fwd_one<2048, true><<<(int)grid, 256, 0, st>>>(a)
+                : fwd_one<2048, false><<<(int)grid, 256, 0, st>>>(a);
+        else
+            return CDMT_E_UNSUPPORTED;
+        return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
+    }
     const long long gcol = bsn * (p->n1 / (4096 / p->n2));
     const long long grow = bsn * (p->n2 / (4096 / p->n1));
     // a dispatch covers at most 2^32 - 1 work-items
@@ -1272,29 +1320,7 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
     return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
 }
 
-// Upper bound of |phase| in half-cycles per unit DM over every bin of the
-// plan (Eq. 1 at the largest offset from nu0 in the lowest subband).  The
-// kernel keeps the integer part of the phase in an int, so |DM| times this
-// must stay below 2^30.
-double max_half_cycles_per_dm(const cdmt_plan_s *p) {
-    const double f_lo = p->f_centre - p->nsub * p->bw / 2;
-    const double half = p->chirp_ref == 0 ? p->bw / (2.0 * p->nchan) : p->bw / 2;
-    const double nu0 = f_lo + half;
-    return 2.0 * 1e6 * kKdm * half * half / (nu0 * nu0 * f_lo);
-}
 
-// True when dm[i] = dm[0] + i (dm[1] - dm[0]) for every i to within tol (the
-// transfer-function recurrence then reproduces each DM's phase to within
-// tol times the largest phase per unit DM).
-bool arithmetic(const double *dm, int n, double tol) {
-    const double step = dm[1] - dm[0];
-    if (step == 0.0)
-        return false;
-    for (int i = 2; i < n; ++i)
-        if (std::fabs(dm[i] - (dm[0] + i * step)) > tol)
-            return false;
-    return true;
-}
 
 // A dispatch covers at most 2^32 - 1 work-items, so large jobs are split into
 // several launches: by DM (at most kMaxDmPerLaunch per launch, passed by
@@ -1446,192 +1472,11 @@ int launch_dv_m(const FusedArgs &a0, double dm, const float *gout, cpair *gin, l
     return CDMT_OK;
 }
 
-long long grad_groups(const cdmt_plan_s *p, int nblock) {
-    const int C = 4096 / p->m;
-    return ((long long)nblock * p->nsub * p->nchan + C - 1) / C;
-}
-
-int check_plan(const cdmt_plan_s *p) { return p ? CDMT_OK : CDMT_E_ARG; }
-
-
-int workspace_bytes(const cdmt_plan_s *p, int nblock, size_t *bytes) {
-    if (nblock < 0)
-        return CDMT_E_ARG;
-    const unsigned long long n = (unsigned long long)nblock * p->nsub * p->nfft;
-    *bytes = (size_t)(2ULL * n * sizeof(cpair));
-    return CDMT_OK;
-}
-
-int check_call(const cdmt_plan_s *p, void *ws, size_t ws_bytes, int nblock) {
-    if (!p)
-        return CDMT_E_ARG;
-    if (nblock < 0)
-        return CDMT_E_ARG;
-    size_t need = 0;
-    workspace_bytes(p, nblock, &need);
-    if (nblock > 0 && (!ws || ws_bytes < need))
-        return ws ? CDMT_E_WORKSPACE : CDMT_E_ARG;
-    const long long chunks = (long long)nblock * p->nsub * p->nchan;
-    if (chunks > 0x7fffffffLL)
-        return CDMT_E_SHAPE;
-    return CDMT_OK;
-}
 
 }  // namespace
 
 extern "C" {
 
-int cdmt_plan(cdmt_plan_t *out, int nsub, double f_centre_mhz, double bw_sub_mhz, int nfft,
-              int noverlap, int nchan, int ndec) {
-    if (!out)
-        return CDMT_E_ARG;
-    *out = nullptr;
-    if (!std::isfinite(f_centre_mhz) || !std::isfinite(bw_sub_mhz))
-        return CDMT_E_ARG;
-    if (nsub < 1 || !is_pow2(nfft) || nfft < 2 || !is_pow2(nchan) || nfft % nchan)
-        return CDMT_E_SHAPE;
-    if (noverlap < 0 || noverlap >= nfft || noverlap % (2 * nchan))
-        return CDMT_E_SHAPE;
-    const int m = nfft / nchan, nd = noverlap / nchan;
-    if (ndec < 1 || (m - nd) % ndec)
-        return CDMT_E_SHAPE;
-    if (!(bw_sub_mhz > 0) || !(f_centre_mhz - nsub * bw_sub_mhz / 2 > 0))
-        return CDMT_E_SHAPE;
-    if (nfft < 4096 || nfft > (1 << 17) || m < 64 || m > 8192)
-        return CDMT_E_UNSUPPORTED;
-    cdmt_plan_s *p = new (std::nothrow) cdmt_plan_s;
-    if (!p)
-        return CDMT_E_ARG;
-    p->nsub = nsub;
-    p->nfft = nfft;
-    p->noverlap = noverlap;
-    p->nchan = nchan;
-    p->ndec = ndec;
-    p->f_centre = f_centre_mhz;
-    p->bw = bw_sub_mhz;
-    p->m = m;
-    p->nd = nd;
-    p->tblk = (m - nd) / ndec;
-    const int l = ilog2(nfft);
-    p->n2 = 1 << (l / 2);
-    p->n1 = nfft / p->n2;
-    *out = p;
-    return CDMT_OK;
-}
-
-int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
-    if (!p)
-        return CDMT_E_ARG;
-    switch (opt) {
-    case CDMT_OPT_INPUT:
-        if (value != 0 && value != 1)
-            return CDMT_E_ARG;
-        p->input_kind = value;
-        return CDMT_OK;
-    case CDMT_OPT_CHIRP_REF:
-        if (value != 0 && value != 1)
-            return CDMT_E_ARG;
-        p->chirp_ref = value;
-        return CDMT_OK;
-    case CDMT_OPT_SIGN:
-        if (value != 1 && value != -1)
-            return CDMT_E_ARG;
-        p->sign = value;
-        return CDMT_OK;
-    case CDMT_OPT_PRECISION:
-        if (value < 0 || value > 2)
-            return CDMT_E_ARG;
-        if (value != 0 && p->m != 4096)
-            return CDMT_E_UNSUPPORTED;
-        p->precision = value;
-        return CDMT_OK;
-    case CDMT_OPT_DM_TILE:
-        if (value < 1 || value > 16)
-            return CDMT_E_ARG;
-        p->dm_tile = value;
-        return CDMT_OK;
-    case CDMT_OPT_CHIRP_EXACT:
-        if (value != 0 && value != 1)
-            return CDMT_E_ARG;
-        p->chirp_exact = value;
-        return CDMT_OK;
-    case CDMT_OPT_LANE_BINS:
-        if (value != 8 && value != 16)
-            return CDMT_E_ARG;
-        p->lane_bins = value;
-        return CDMT_OK;
-    case CDMT_OPT_FWD_N2:
-        if (!fwd_split_ok(p->nfft, value))
-            return CDMT_E_ARG;
-        p->n2 = value;
-        p->n1 = p->nfft / value;
-        return CDMT_OK;
-    case CDMT_OPT_OUT_LAYOUT:
-        if (value != 0 && value != 1)
-            return CDMT_E_ARG;
-        p->out_layout = value;
-        return CDMT_OK;
-    default:
-        return CDMT_E_ARG;
-    }
-}
-
-int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
-    if (!p || !value)
-        return CDMT_E_ARG;
-    switch (opt) {
-    case CDMT_OPT_INPUT: *value = p->input_kind; return CDMT_OK;
-    case CDMT_OPT_CHIRP_REF: *value = p->chirp_ref; return CDMT_OK;
-    case CDMT_OPT_SIGN: *value = p->sign; return CDMT_OK;
-    case CDMT_OPT_PRECISION: *value = p->precision; return CDMT_OK;
-    case CDMT_OPT_DM_TILE: *value = p->dm_tile; return CDMT_OK;
-    case CDMT_OPT_CHIRP_EXACT: *value = p->chirp_exact; return CDMT_OK;
-    case CDMT_OPT_LANE_BINS: *value = p->lane_bins; return CDMT_OK;
-    case CDMT_OPT_FWD_N2: *value = p->n2; return CDMT_OK;
-    case CDMT_OPT_OUT_LAYOUT: *value = p->out_layout; return CDMT_OK;
-    default: return CDMT_E_ARG;
-    }
-}
-
-int cdmt_noverlap_for(double f_lo_mhz, double bw_sub_mhz, double dm_max, int nchan, int ndec,
-                      int chirp_ref, int *noverlap_out) {
-    if (!noverlap_out || !std::isfinite(f_lo_mhz) || !std::isfinite(bw_sub_mhz) ||
-        !std::isfinite(dm_max))
-        return CDMT_E_ARG;
-    if (!(f_lo_mhz > 0) || !(bw_sub_mhz > 0) || dm_max < 0 || !is_pow2(nchan) || ndec < 1 ||
-        (chirp_ref != 0 && chirp_ref != 1))
-        return CDMT_E_ARG;
-    // Eq. 2 over the lowest channel (or the lowest subband), then
-    // n_d n_c = r t_d subband samples (Sec. 2), r = bw in samples/s
-    const double hi = f_lo_mhz + (chirp_ref == 0 ? bw_sub_mhz / nchan : bw_sub_mhz);
-    const double td = kKdm * (1.0 / (f_lo_mhz * f_lo_mhz) - 1.0 / (hi * hi)) * dm_max;
-    const double need = std::ceil(bw_sub_mhz * 1e6 * td - 1e-9);
-    const long long unit = 2LL * nchan * ndec;
-    const long long nov = ((long long)need + unit - 1) / unit * unit;
-    if (nov > 0x7fffffffLL)
-        return CDMT_E_SHAPE;
-    *noverlap_out = (int)nov;
-    return CDMT_OK;
-}
-
-int cdmt_output_shape(cdmt_plan_t p, int nblock, long long *ntime_in, long long *ntime_out,
-                      int *nchan_out) {
-    if (check_plan(p) || nblock < 0)
-        return CDMT_E_ARG;
-    if (ntime_in)
-        *ntime_in = (long long)nblock * (p->nfft - p->noverlap) + p->noverlap;
-    if (ntime_out)
-        *ntime_out = (long long)nblock * p->tblk;
-    if (nchan_out)
-        *nchan_out = p->nsub * p->nchan;
-    return CDMT_OK;
-}
-
-int cdmt_workspace_size(cdmt_plan_t p, int nblock, size_t *bytes) {
-    if (check_plan(p) || !bytes)
-        return CDMT_E_ARG;
-    return workspace_bytes(p, nblock, bytes);
-}
 
 int cdmt_forward(cdmt_plan_t p, void *ws, size_t ws_bytes, const void *voltages, int nblock,
                  void *hip_stream) {
@@ -1658,10 +1503,8 @@ int cdmt_dedisperse_spectra(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock
         return CDMT_OK;
     if (!dm_list || !out)
         return CDMT_E_ARG;
-    const double bound = max_half_cycles_per_dm(p);
-    for (int i = 0; i < ndm; ++i)
-        if (!std::isfinite(dm_list[i]) || std::fabs(dm_list[i]) * bound >= 1073741824.0)
-            return CDMT_E_ARG;
+    if ((st = check_dms(p, dm_list, ndm)))
+        return st;
     if ((st = ensure_twiddles()))
         return st;
     return launch_dedisperse(p, ws, nblock, dm_list, ndm, out, (hipStream_t)hip_stream);
@@ -1678,23 +1521,13 @@ int cdmt_dedisperse(cdmt_plan_t p, void *ws, size_t ws_bytes, const void *voltag
         return CDMT_OK;
     if (!voltages || !dm_list || !out)
         return CDMT_E_ARG;
-    const double bound = max_half_cycles_per_dm(p);
-    for (int i = 0; i < ndm; ++i)
-        if (!std::isfinite(dm_list[i]) || std::fabs(dm_list[i]) * bound >= 1073741824.0)
-            return CDMT_E_ARG;
+    if ((st = check_dms(p, dm_list, ndm)))
+        return st;
     if ((st = cdmt_forward(p, ws, ws_bytes, voltages, nblock, hip_stream)))
         return st;
     return cdmt_dedisperse_spectra(p, ws, ws_bytes, nblock, dm_list, ndm, out, hip_stream);
 }
 
-int cdmt_gradient_workspace_size(cdmt_plan_t p, int nblock, int ndm, size_t *bytes) {
-    if (!p || !bytes || nblock < 0 || ndm < 0)
-        return CDMT_E_ARG;
-    if (p->m > 4096)
-        return CDMT_E_UNSUPPORTED;
-    *bytes = (size_t)ndm * (size_t)grad_groups(p, nblock) * sizeof(double);
-    return CDMT_OK;
-}
 
 int cdmt_dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const double *dm_list,
                      int ndm, const float *grad_out, void *gws, size_t gws_bytes, double *dldm,
@@ -1710,10 +1543,8 @@ int cdmt_dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const
         return CDMT_OK;
     if (!dm_list || !grad_out || !gws || !dldm)
         return CDMT_E_ARG;
-    const double bound = max_half_cycles_per_dm(p);
-    for (int i = 0; i < ndm; ++i)
-        if (!std::isfinite(dm_list[i]) || std::fabs(dm_list[i]) * bound >= 1073741824.0)
-            return CDMT_E_ARG;
+    if ((st = check_dms(p, dm_list, ndm)))
+        return st;
     size_t need = 0;
     cdmt_gradient_workspace_size(p, nblock, ndm, &need);
     if (gws_bytes < need)
@@ -1736,16 +1567,6 @@ int cdmt_dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const
     }
 }
 
-int cdmt_voltage_gradient_workspace_size(cdmt_plan_t p, int nblock, size_t *bytes) {
-    if (!p || !bytes || nblock < 0)
-        return CDMT_E_ARG;
-    if (p->m > 4096)
-        return CDMT_E_UNSUPPORTED;
-    size_t w = 0;
-    workspace_bytes(p, nblock, &w);
-    *bytes = w / 2 * 3;                  // spectrum gradient + the forward kernels' two buffers
-    return CDMT_OK;
-}
 
 int cdmt_voltage_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, double dm,
                           const float *grad_out, void *gws, size_t gws_bytes, float *grad_v,
@@ -1761,8 +1582,8 @@ int cdmt_voltage_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, 
         return CDMT_OK;
     if (!grad_out || !gws || !grad_v)
         return CDMT_E_ARG;
-    if (!std::isfinite(dm) || std::fabs(dm) * max_half_cycles_per_dm(p) >= 1073741824.0)
-        return CDMT_E_ARG;
+    if ((st = check_dms(p, &dm, 1)))
+        return st;
     size_t need = 0;
     cdmt_voltage_gradient_workspace_size(p, nblock, &need);
     if (gws_bytes < need)
@@ -1803,19 +1624,6 @@ int cdmt_voltage_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, 
     return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
 }
 
-void cdmt_destroy(cdmt_plan_t p) { delete p; }
-
-const char *cdmt_status_string(int status) {
-    switch (status) {
-    case CDMT_OK: return "ok";
-    case CDMT_E_ARG: return "invalid argument";
-    case CDMT_E_SHAPE: return "shape violates the method's constraints";
-    case CDMT_E_WORKSPACE: return "workspace too small";
-    case CDMT_E_DEVICE: return "HIP device error";
-    case CDMT_E_UNSUPPORTED: return "configuration not supported by this library";
-    default: return "unknown status";
-    }
-}
 
 }  // extern "C"
 
@@ -1865,10 +1673,9 @@ int batch_layout(const cdmt_beam_t *beams, int nbeam, std::vector<size_t> *spec_
             return CDMT_E_UNSUPPORTED;          // 512-lane workgroups: use cdmt_dedisperse
         if ((long long)B.nblock * p->nsub * p->nchan > 0x7fffffffLL)
             return CDMT_E_SHAPE;
-        const double bound = max_half_cycles_per_dm(p);
-        for (int i = 0; i < B.ndm; ++i)
-            if (!std::isfinite(B.dm_list[i]) || std::fabs(B.dm_list[i]) * bound >= 1073741824.0)
-                return CDMT_E_ARG;
+        const int dst = check_dms(p, B.dm_list, B.ndm);
+        if (dst)
+            return dst;
         size_t w = 0;
         workspace_bytes(p, B.nblock, &w);
         if (spec_off)

@@ -10,6 +10,7 @@
 
 #include "../../include/cdmt.h"
 #include "plan.hpp"
+#include "xcd.hpp"
 
 using cdmt::kKdm;
 using cdmt::xcd_remap;

@@ -67,7 +67,7 @@ def test_plan_validation(lib):
         "bw <= 0": (GOOD[:2] + (-0.1,) + GOOD[3:], cdmt.CDMT_E_SHAPE),
         "band below 0": ((8, 0.5) + GOOD[2:], cdmt.CDMT_E_SHAPE),
         "nan centre": ((8, float("nan")) + GOOD[2:], cdmt.CDMT_E_ARG),
-        "nfft too small": (GOOD[:3] + (2048, 0, 8, 1), cdmt.CDMT_E_UNSUPPORTED),
+        "nfft too small": (GOOD[:3] + (512, 0, 8, 1), cdmt.CDMT_E_UNSUPPORTED),
         "nfft too large": (GOOD[:3] + (1 << 18, 0, 8, 1), cdmt.CDMT_E_UNSUPPORTED),
         "M too small": (GOOD[:3] + (16384, 0, 512, 1), cdmt.CDMT_E_UNSUPPORTED),
         "M too large": (GOOD[:3] + (1 << 17, 0, 8, 1), cdmt.CDMT_E_UNSUPPORTED),
@@ -358,3 +358,118 @@ def test_incoherent_validation(lib):
         assert f(p, 4, P, arr, 3, -0.5, 0.01, 101, P, z.value, None, None) == cdmt.CDMT_E_ARG
     finally:
         cdmt.cdmt_destroy(p)
+
+
+def _eq2_limit(f_lo, bw, nchan, nov, chirp_ref):
+    """Largest DM whose Eq. 2 sweep (Sec. 2) over the lowest channel (or
+    subband), times the sample rate bw, is at most the overlap."""
+    hi = f_lo + (bw / nchan if chirp_ref == cdmt.CHIRP_CHANNEL else bw)
+    return nov / (bw * 1e6 * oracle.sweep_seconds(f_lo, hi, 1.0))
+
+
+def test_dm_limit_is_eq2_for_the_overlap(lib):
+    """cdmt_dm_limit inverts the overlap sizing of Sec. 2 / Eq. 2: the LOFAR
+    plan (overlap sized for DM 63.5 over the lowest subband) supports its
+    128 trials in both nu0 modes, and cdmt_noverlap_for at the limit gives
+    back the plan's overlap."""
+    import ctypes
+    w = synth.LOFAR
+    f_lo = w.f_centre - w.nsub * w.bw / 2
+    for ref in (cdmt.CHIRP_CHANNEL, cdmt.CHIRP_SUBBAND):
+        p = cdmt.cdmt_plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+        try:
+            cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_CHIRP_REF, ref)
+            lim = cdmt.cdmt_dm_limit(p)
+            assert lim == pytest.approx(_eq2_limit(f_lo, w.bw, w.nchan, w.noverlap, ref),
+                                        rel=1e-12)
+            assert lim >= 63.5
+            nov = cdmt.cdmt_noverlap_for(f_lo, w.bw, lim, w.nchan, w.ndec, ref)
+            assert nov == w.noverlap
+        finally:
+            cdmt.cdmt_destroy(p)
+    # nu0 per subband: the subband-wide sweep of DM 63.5 is 15114.5 samples
+    p = cdmt.cdmt_plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+    try:
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_CHIRP_REF, cdmt.CHIRP_SUBBAND)
+        assert 63.5 * w.noverlap / 15115 < cdmt.cdmt_dm_limit(p) < 63.5 * w.noverlap / 15114
+    finally:
+        cdmt.cdmt_destroy(p)
+    v = ctypes.c_double()
+    assert lib.cdmt_dm_limit(None, ctypes.byref(v)) == cdmt.CDMT_E_ARG
+
+
+def test_dm_beyond_the_overlap_is_rejected(lib):
+    """Every call that takes DMs rejects |DM| above cdmt_dm_limit with
+    CDMT_E_SHAPE before any device work, accepts DM 63.5 and the limit
+    itself on the LOFAR plan (nu0 per subband), and CDMT_OPT_DM_CHECK = 0
+    lifts the check."""
+    import ctypes
+    import math
+    w = synth.LOFAR
+    p = cdmt.cdmt_plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
+    try:
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_CHIRP_REF, cdmt.CHIRP_SUBBAND)
+        assert cdmt.cdmt_plan_get(p, cdmt.CDMT_OPT_DM_CHECK) == 1
+        lim = cdmt.cdmt_dm_limit(p)
+        past = math.nextafter(lim * (1 + 1e-12), math.inf)
+        P = ctypes.c_void_p(256)
+        big = 1 << 44
+        arr = lambda *d: (ctypes.c_double * len(d))(*d)
+        beams = lambda d: (cdmt.Beam * 1)(cdmt.Beam(p, 1, P.value, d, len(d), P.value))
+        z = ctypes.c_size_t()
+        # the batch sizing validates DM lists without touching the device
+        for good in (arr(0.0, 63.5), arr(lim), arr(-lim)):
+            assert lib.cdmt_batch_workspace_size(beams(good), 1, ctypes.byref(z)) == cdmt.CDMT_OK
+        for bad in (arr(0.0, past), arr(-past)):
+            assert lib.cdmt_batch_workspace_size(beams(bad), 1, ctypes.byref(z)) == \
+                cdmt.CDMT_E_SHAPE
+            n = len(bad)
+            assert lib.cdmt_dedisperse_spectra(p, P, big, 1, bad, n, P, None) == cdmt.CDMT_E_SHAPE
+            assert lib.cdmt_dedisperse(p, P, big, P, 1, bad, n, P, None) == cdmt.CDMT_E_SHAPE
+            assert lib.cdmt_dm_gradient(p, P, big, 1, bad, n, P, P, big, P,
+                                        None) == cdmt.CDMT_E_SHAPE
+            h = ctypes.c_void_p()
+            assert lib.cdmt_batch_create(ctypes.byref(h), beams(bad), 1, P, big) == \
+                cdmt.CDMT_E_SHAPE
+        assert lib.cdmt_voltage_gradient(p, P, big, 1, past, P, P, big, P, 0,
+                                         None) == cdmt.CDMT_E_SHAPE
+        cdmt.cdmt_plan_set(p, cdmt.CDMT_OPT_DM_CHECK, 0)
+        assert lib.cdmt_batch_workspace_size(beams(arr(0.0, past, 2 * lim)), 1,
+                                             ctypes.byref(z)) == cdmt.CDMT_OK
+        assert lib.cdmt_plan_set(p, cdmt.CDMT_OPT_DM_CHECK, 2) == cdmt.CDMT_E_ARG
+    finally:
+        cdmt.cdmt_destroy(p)
+
+
+def test_nfft_range_is_2_10_to_2_17(lib):
+    """N_bin from 2^10 (one-pass forward transform) to 2^17 is accepted."""
+    for nfft, nchan in ((1024, 8), (2048, 8), (4096, 8), (1 << 17, 16)):
+        assert _plan_status(2, 120.0, 0.1953125, nfft, 256, nchan, 4) == cdmt.CDMT_OK, nfft
+    assert _plan_status(2, 120.0, 0.1953125, 512, 0, 8, 4) == cdmt.CDMT_E_UNSUPPORTED
+    assert _plan_status(2, 120.0, 0.1953125, 1 << 18, 256, 8, 4) == cdmt.CDMT_E_UNSUPPORTED
+    p = cdmt.cdmt_plan(2, 120.0, 0.1953125, 2048, 256, 8, 4)
+    try:
+        # one pass: no four-step split to choose
+        assert cdmt.load().cdmt_plan_set(p, cdmt.CDMT_OPT_FWD_N2, 64) == cdmt.CDMT_E_ARG
+    finally:
+        cdmt.cdmt_destroy(p)
+
+
+def test_binding_checks_out_and_workspace_before_any_launch(lib):
+    """Plan.dedisperse_spectra takes an output tensor the C call cannot size:
+    a wrong dtype, shape, layout or device raises ValueError before the
+    library is called (CPU tensors here, so nothing can launch)."""
+    import torch
+    plan = cdmt.Plan(*GOOD)
+    ws = torch.empty(16, dtype=torch.uint8)
+    shape = plan.out_shape(2, 1)
+    good_shape = torch.empty(shape, dtype=torch.float32)
+    for out in (torch.empty(shape, dtype=torch.float64),
+                torch.empty((2, shape[1] - 1, shape[2]), dtype=torch.float32),
+                torch.empty((2, shape[2], shape[1]), dtype=torch.float32).transpose(1, 2),
+                torch.empty((1,) + shape[1:], dtype=torch.float32),
+                good_shape):                                     # right shape, not on the device
+        with pytest.raises(ValueError):
+            plan.dedisperse_spectra(1, [0.0, 1.0], out, ws)
+    with pytest.raises(ValueError):
+        plan._check_workspace(torch.empty(4, dtype=torch.float32))

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from conftest import allow_short_overlap
 from paper_1607_00909_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -57,6 +58,7 @@ def _voltages(cfg, nblock, sigma, seed, kind, pulses=()):
 def _run_gpu(hip_lib, cfg, v, nblock, dms, kind, **kw):
     torch = _torch()
     plan = _plan(hip_lib, cfg, kind, **kw)
+    allow_short_overlap(plan, dms)
     xd = torch.from_numpy(v).cuda()
     out = plan.dedisperse(xd, nblock, list(dms))
     torch.cuda.synchronize()
@@ -108,6 +110,9 @@ CASES = [
     (2, 65536, 15360, 16, 8, 2, "ci8", oracle.SUBBAND, -1, 9, 8, 8), # same, 8 bins per lane
     (1, 32768, 4096, 16, 2, 2, "cf32", oracle.CHANNEL, 1, 5, 2, 8),  # M = 2048, 8 bins per lane
     (1, 131072, 16384, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 3, 1),  # M = 8192, nfft 2^17
+    (3, 1024, 256, 8, 2, 3, "ci8", oracle.CHANNEL, -1, 5, 4),        # nfft 2^10, one-pass forward
+    (2, 2048, 512, 16, 4, 3, "cf32", oracle.SUBBAND, 1, 6, 3),       # nfft 2^11, M = 128
+    (5, 2048, 256, 2, 4, 2, "ci8", oracle.SUBBAND, -1, 4, 16),       # nfft 2^11, M = 1024
 ]
 
 
@@ -175,6 +180,7 @@ def test_channel_major_layout_is_the_transpose(hip_lib, case):
     for layout in (0, 1):
         kw = {k: val for k, val in opts.items() if k != "precision"}
         plan = _plan(hip_lib, cfg, "ci8", out_layout=layout, **kw)
+        allow_short_overlap(plan, dms)
         if "precision" in opts:
             hip_lib.cdmt_plan_set(plan.handle, hip_lib.CDMT_OPT_PRECISION, opts["precision"])
         outs.append(plan.dedisperse(v, 2, dms))
