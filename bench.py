@@ -80,9 +80,11 @@ def fused_flops_per_bin(m: int) -> float:
     return 2 * (6 + 5 * math.log2(m) + 3)
 
 
-def cpu_baseline(w, x_dev, npairs: int, threads: int, outputs=None):
+def cpu_baseline(w, x_dev, npairs: int, threads: int, outputs=None, pulses=()):
     """Oracle (FP64, C) on a bounded sample of (subband, block) pairs with all
-    DMs, extrapolated linearly to the whole job."""
+    DMs, extrapolated linearly to the whole job; the sample includes the
+    block of every injected pulse (at a spread of subbands), and the GPU
+    outputs are compared with the oracle on every pair."""
     import numpy as np
 
     import oracle
@@ -90,10 +92,14 @@ def cpu_baseline(w, x_dev, npairs: int, threads: int, outputs=None):
 
     cfg = oracle.Config(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec)
     pairs = []
-    for i in range(npairs):
-        s = (i * 97) % w.nsub
-        b = (i * 7) % w.nblock
-        pairs.append((s, b))
+    for i, (_, t0) in enumerate(pulses):
+        pairs.append(((i * 61 + 11) % w.nsub, t0 // w.tblk))
+    i = 0
+    while len(pairs) < npairs:
+        sb = ((i * 97) % w.nsub, (i * 7) % w.nblock)
+        if sb not in pairs:
+            pairs.append(sb)
+        i += 1
     subs = sorted({s for s, _ in pairs})
     host = {s: x_dev[s].cpu().numpy() for s in subs}
 
@@ -228,6 +234,147 @@ def gradient_leg(cdmt, synth, torch, dev, steps: int):
             "gradient_dm_s_per_s": round(len(dms) * data_s / (adj / 1e3), 1)}
 
 
+K_DM = 1.0 / 2.41e-4          # Sec. 2, after Eq. 1
+
+
+def dispersed_pulses(torch, x, cfg, chirp_ref: int, sign: int, pulses, amp: float,
+                     width: float = 0.0) -> int:
+    """Input synthesis for the pulse measurements (the recipe of the test
+    suite's injection, on the device): for each (dm, t0), a real pulse of
+    energy amp^2 per polarisation centred on output sample t0, dispersed by the
+    inverse of the plan's transfer function (Eq. 1 with the plan's nu0, per
+    channel or per subband), on an nfft-sample window, added to both
+    polarisations of float32 voltages x [nsub][ntime][2][2] in place.  The
+    pulse is an impulse (width 0) or a Gaussian of standard deviation `width`
+    samples (its spectrum tapered accordingly); FP64 arithmetic, torch FFTs.
+    Returns the number of samples where the window was cut at the stream ends."""
+    import math
+    dev = x.device
+    nsub, ntime = x.shape[0], x.shape[1]
+    L = cfg["nfft"]
+    bw, nchan = cfg["bw"], cfg["nchan"]
+    k = torch.arange(L, device=dev)
+    j = (k + L // 2) % L                                   # swapped index of FFT bin k
+    rel = (j.double() - L / 2) * bw / L                    # MHz from the subband centre
+    freq = torch.fft.fftfreq(L, device=dev, dtype=torch.float64)      # cycles per sample
+    taper = torch.exp(-0.5 * (2 * math.pi * width * freq) ** 2)
+    norm = amp / math.sqrt(float((taper ** 2).sum()) / L)  # energy amp^2 whatever the width
+    impulse = norm * taper * (1.0 - 2.0 * (k % 2).double())    # centred at L / 2
+    cut = 0
+    for dm, t0 in pulses:
+        n0 = cfg["noverlap"] // 2 + t0 * nchan * cfg["ndec"] + nchan * cfg["ndec"] // 2
+        w0 = n0 - L // 2
+        lo, hi = max(0, -w0), min(L, ntime - w0)
+        cut += L - (hi - lo)
+        for s0 in range(0, nsub, 32):
+            s1 = min(nsub, s0 + 32)
+            fs = cfg["f_centre"] + (torch.arange(s0, s1, device=dev).double() - (nsub - 1) / 2) * bw
+            if chirp_ref == 0:
+                ch = torch.div(j, L // nchan, rounding_mode="floor").double()
+                nu0 = fs[:, None] - bw / 2 + (ch[None, :] + 0.5) * bw / nchan
+                nu = rel[None, :] - (nu0 - fs[:, None])
+            else:
+                nu0 = fs[:, None].expand(-1, L)
+                nu = rel[None, :].expand(s1 - s0, -1)
+            cyc = 1e6 * K_DM * dm * nu * nu / (nu0 * nu0 * (nu0 + nu))
+            spec = impulse[None, :] * torch.exp(torch.complex(torch.zeros_like(cyc),
+                                                              -sign * 2 * math.pi * cyc))
+            wav = torch.fft.ifft(spec, dim=1)[:, lo:hi]
+            seg = x[s0:s1, w0 + lo:w0 + hi]
+            seg[..., 0] += wav.real.float()[:, :, None]
+            seg[..., 1] += wav.imag.float()[:, :, None]
+    return cut
+
+
+def pulse_snr(torch, fb, t0: int) -> float:
+    """S/N of a pulse at output sample t0 of one DM's filterbank [t][ch]:
+    (series[t0] - median) / (1.4826 MAD) of the channel-summed series."""
+    s = fb.double().sum(dim=1)
+    med = s.median()
+    mad = (s - med).abs().median()
+    return float((s[t0] - med) / (1.4826 * mad))
+
+
+def refine_leg(cdmt, synth, torch, dev, ncand: int = 64, max_iter: int = 40):
+    """DM refinement of candidates by gradient ascent: ncand candidates, each
+    its own ~1 s segment (4 blocks) of the LOFAR-shaped setup (288 subbands,
+    complex float32 noise sigma 1, N_bin 65536, overlap 15360, 16 channels,
+    x8, nu0 per subband) with a pulse (S/N ~30) at a random continuous DM in
+    [5, 60).  From the nearest trial of the 0.5-step coarse grid, the DM moves
+    along d(S/N)/dDM (the differentiable DM stage, adjoint per block, spectra
+    recomputed, never stored) with a step that grows by 1.5 after a gain and
+    shrinks by 0.3 otherwise, until it moves less than 1e-4 pc cm^-3.  S/N is
+    (s[t] - mean) / std of the channel-summed series s at the sample t where
+    the coarse trial peaks."""
+    import math
+    w = synth.LOFAR
+    nblock = 4
+    plan = cdmt.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                     input_kind=cdmt.INPUT_CF32, chirp_ref=cdmt.CHIRP_SUBBAND, chirp_exact=1)
+    ntin, ntout, nch = plan.shape(nblock)
+    cfg = {"nfft": w.nfft, "noverlap": w.noverlap, "nchan": w.nchan, "ndec": w.ndec,
+           "bw": w.bw, "f_centre": w.f_centre}
+    ws = plan.workspace(nblock, dev)
+    tblk = (w.m - w.nd) // w.ndec
+    errs, coarse_errs, iters, ms_each, evals = [], [], [], [], []
+    for i, (dm_true, r_t, seed) in enumerate(synth.candidate_draws(ncand)):
+        t0 = tblk + r_t % (2 * tblk)                 # inside blocks 1-2 of 4
+        x = synth.device_noise("cf32", w.nsub, ntin, 1.0, seed, dev)
+        dispersed_pulses(torch, x, cfg, 1, -1, [(dm_true, t0)], 90.0)
+        plan.forward(x, nblock, ws)
+        del x
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        dm_c = round(dm_true * 2.0) / 2.0
+        with torch.no_grad():
+            f0 = cdmt.dedisperse_dm(plan, torch.tensor([dm_c], dtype=torch.float64), nblock, ws)
+            tpk = int(f0[0].double().sum(dim=1).argmax())
+
+        def snr_grad(dm):
+            d = torch.tensor([dm], dtype=torch.float64, requires_grad=True)
+            F = cdmt.dedisperse_dm(plan, d, nblock, ws)
+            sr = F[0].double().sum(dim=1)
+            snr = (sr[tpk] - sr.mean()) / sr.std(correction=0)
+            snr.backward()
+            return float(snr.detach()), float(d.grad[0])
+
+        dm, S, g = dm_c, *snr_grad(dm_c)
+        step = 0.25 / max(abs(g), 1e-30)
+        n_eval, it = 1, 0
+        for it in range(1, max_iter + 1):
+            cand = dm + step * g
+            Sc, gc = snr_grad(cand)
+            n_eval += 1
+            if Sc > S:
+                dm, S, g = cand, Sc, gc
+                step *= 1.5
+            else:
+                step *= 0.3
+            if abs(step * g) < 1e-4:
+                break
+        torch.cuda.synchronize()
+        ms_each.append((time.perf_counter() - t_start) * 1e3)
+        errs.append(abs(dm - dm_true))
+        coarse_errs.append(abs(dm_c - dm_true))
+        iters.append(it)
+        evals.append(n_eval)
+    del ws
+    torch.cuda.empty_cache()
+    med = lambda v: sorted(v)[len(v) // 2]
+    data_s = cdmt.dm_seconds(nblock, w.nfft, w.noverlap, w.bw)
+    res = {"workload": f"refine-{ncand}cand-{w.nsub}sub-1s", "candidates": ncand,
+           "data_seconds_each": round(data_s, 4), "chirp_ref": "subband",
+           "abs_err_median": med(errs), "abs_err_max": max(errs),
+           "coarse_abs_err_median": med(coarse_errs),
+           "iterations_mean": round(sum(iters) / len(iters), 2),
+           "evaluations_mean": round(sum(evals) / len(evals), 2),
+           "ms_per_refinement_median": round(med(ms_each), 2),
+           "ms_per_evaluation": round(sum(ms_each) / sum(evals), 3)}
+    log(f"refine: {ncand} candidates, |DM - true| median {res['abs_err_median']:.2e} max "
+        f"{res['abs_err_max']:.2e}, {res['ms_per_refinement_median']} ms each")
+    return res
+
+
 def copy_bandwidth(torch, dev, nbytes: int = 4 << 30, reps: int = 5) -> float:
     """Measured device-to-device copy rate (bytes read + written per second):
     the practical HBM ceiling that the kernels are also compared with."""
@@ -331,6 +478,10 @@ def main():
                     help="also time the 8-bit redigitisation of the filterbank")
     ap.add_argument("--incoherent", action=argparse.BooleanOptionalAction, default=True,
                     help="also time the incoherent stage of a semi-coherent search")
+    ap.add_argument("--pulse-amp-sigma", type=float, default=62.5,
+                    help="amplitude of the injected pulses in units of the noise sigma")
+    ap.add_argument("--refine", action=argparse.BooleanOptionalAction, default=True,
+                    help="also refine 64 pulse candidates' DMs by gradient ascent")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter calibration for profiles)")
     args = ap.parse_args()
@@ -350,10 +501,30 @@ def main():
         sys.exit(1)
     w = synth.WORKLOADS[args.workload]
     dev = torch.device("cuda:0")
-    log(f"workload {w.name}: generating {w.nsub}x{w.ntime_in} {w.input_kind} voltages on device")
-    x = synth.device_noise(w.input_kind, w.nsub, w.ntime_in, w.sigma, w.seed, dev)
     kind = cdmt.INPUT_CI8 if w.input_kind == "ci8" else cdmt.INPUT_CF32
     chirp_ref = cdmt.CHIRP_CHANNEL if args.chirp_ref == "channel" else cdmt.CHIRP_SUBBAND
+    log(f"workload {w.name}: generating {w.nsub}x{w.ntime_in} {w.input_kind} voltages on device")
+    # noise (FP32 on the device), the workload's dispersed pulses added in
+    # FP32, then the 8-bit quantisation (rint, clip to +-127) where the input
+    # is int8: the same bytes for every precision and for the oracle
+    x = synth.device_noise("cf32", w.nsub, w.ntime_in, w.sigma, w.seed, dev)
+    pulses = synth.pulse_draws(w)
+    pcfg = {"nfft": w.nfft, "noverlap": w.noverlap, "nchan": w.nchan, "ndec": w.ndec,
+            "bw": w.bw, "f_centre": w.f_centre}
+    # Gaussian pulses of 64 input samples (half an output sample) with S/N ~15
+    # in the channel sum of the 4608-channel filterbank
+    pulse_amp = args.pulse_amp_sigma * w.sigma
+    dispersed_pulses(torch, x, pcfg, chirp_ref, -1, pulses, pulse_amp, width=64.0)
+    clipped = 0
+    if w.input_kind == "ci8":
+        clipped = int((x.abs() > 127.5).sum())
+        x8 = torch.empty(x.shape, dtype=torch.int8, device=dev)
+        for s0 in range(0, w.nsub, 16):
+            x8[s0:s0 + 16] = torch.clamp(torch.round(x[s0:s0 + 16]), -127, 127).to(torch.int8)
+        del x
+        x = x8
+        torch.cuda.empty_cache()
+    log(f"{len(pulses)} pulses injected (amplitude {pulse_amp:g}), {clipped} components clipped")
     plan = cdmt.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
                      input_kind=kind, chirp_ref=chirp_ref, dm_tile=args.dm_tile,
                      lane_bins=args.lane_bins)
@@ -455,13 +626,21 @@ def main():
     }
     outputs = {args.precision: out}
     o2 = None
+    dm_index = {d: i for i, d in enumerate(dms)}
+    snr = {args.precision: [pulse_snr(torch, out[dm_index[dm]], t0) for dm, t0 in pulses]}
+    line["pulses"] = {"injected": [{"dm": dm, "t0": t0} for dm, t0 in pulses],
+                      "amplitude": pulse_amp, "gaussian_width_samples": 64,
+                      "clipped_components": clipped}
     if args.variants and w.m == 4096:
-        # the same job with the other backward-FFT arithmetics, same input
+        # the same job with the other backward-FFT arithmetics, and with the
+        # transfer function evaluated afresh for every DM, same input
         variants = {}
-        for name, code in (("fp32", 0), ("bf16x3", 1), ("fp16x3", 2)):
+        for name, code in (("fp32", 0), ("bf16x3", 1), ("fp16x3", 2), ("fp32-exact", 0)):
             if name == args.precision:
                 continue
             cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, code)
+            cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_CHIRP_EXACT,
+                               1 if name == "fp32-exact" else 0)
             o2 = torch.empty_like(out)
             plan.dedisperse_spectra(w.nblock, dms, o2, ws)
             torch.cuda.synchronize()
@@ -483,17 +662,31 @@ def main():
                               "fused_ms": round(ms, 3),
                               "normwise_vs_" + args.precision: rel}
             if code != 0:
+                # the method's flops (the FP32 accounting above) against the
+                # matrix-core peak, and the matrix flops the kernel issues
+                # (dense 32x32 DFT blocks, three split products)
                 mflops = mx_mfma_flops_per_chunk_dm() * w.nblock * w.nsub * w.nchan * ndm
-                ach = mflops / (ms / 1e3) / 1e12
+                ach = flops / (ms / 1e3) / 1e12
+                iss = mflops / (ms / 1e3) / 1e12
                 variants[name]["roofline"] = {
-                    "kernel": "fused_dedisperse_mx", "bound": "mfma", "achieved": round(ach, 1),
+                    "kernel": "fused_dedisperse_mx", "bound": "mfma", "achieved": round(ach, 2),
                     "peak": MFMA_F16_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(ach / MFMA_F16_PEAK_TFLOPS, 4),
+                    "issued_achieved": round(iss, 1),
+                    "issued_frac": round(iss / MFMA_F16_PEAK_TFLOPS, 4),
                     "traffic": measured_traffic("fused_dedisperse_mx<%s>" % name)}
+            snr[name] = [pulse_snr(torch, o2[dm_index[dm]], t0) for dm, t0 in pulses]
             outputs[name] = o2
             log(f"variant {name}: fused {ms:.3f} ms, normwise vs {args.precision} {rel:.2e}")
         cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_PRECISION, prec_code)
+        cdmt.cdmt_plan_set(plan.handle, cdmt.CDMT_OPT_CHIRP_EXACT, 0)
         line["variants"] = variants
+    base = snr.get("fp32")
+    line["pulses"]["snr"] = {k: [round(v, 4) for v in vals] for k, vals in snr.items()}
+    if base:
+        line["pulses"]["snr_loss_vs_fp32"] = {
+            k: max(abs(1.0 - v / b) for v, b in zip(vals, base))
+            for k, vals in snr.items() if k != "fp32"}
     if args.redigitise:
         # 8-bit redigitisation of the FP32 filterbank (the paper's step after the
         # transpose), timed on its own: two reads of the filterbank, one byte write
@@ -525,9 +718,15 @@ def main():
         log(f"incoherent: {line['incoherent']['ms']:.3f} ms")
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
-        threads = min(16, os.cpu_count() or 1)
-        log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads")
-        line["cpu_baseline"], errs = cpu_baseline(w, x, args.cpu_pairs, threads, outputs)
+        # every core this process may run on, up to the GPU machine's CPU share
+        # of 16 (the pool is sized to that share whatever the host shows)
+        avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+        threads = min(16, avail)
+        log(f"cpu baseline: oracle on {args.cpu_pairs} (subband, block) pairs, {threads} threads "
+            f"(nproc {os.cpu_count()}, affinity {avail})")
+        line["cpu_baseline"], errs = cpu_baseline(w, x, args.cpu_pairs, threads, outputs, pulses)
+        line["cpu_baseline"]["host_nproc"] = os.cpu_count()
+        line["cpu_baseline"]["affinity_cores"] = avail
         line["errors_vs_oracle"] = errs
     if args.batch:
         # free the single-job buffers first: the batch holds ~125 GB of its own
@@ -539,6 +738,8 @@ def main():
         torch.cuda.empty_cache()
     if args.gradient:
         line["gradient"] = gradient_leg(cdmt, synth, torch, dev, args.steps)
+    if args.refine:
+        line["refine"] = refine_leg(cdmt, synth, torch, dev)
     print(json.dumps(line), flush=True)
 
 

@@ -69,11 +69,19 @@ enum cdmt_opt {
                                 1: [DM][channel][time], which the incoherent stage
                                 reads without its own transpose.  Same values either
                                 way, bit for bit                                        */
-    CDMT_OPT_DM_CHECK = 9    /* 1 (default): every call that takes DMs rejects, with
+    CDMT_OPT_DM_CHECK = 9,   /* 1 (default): every call that takes DMs rejects, with
                                 CDMT_E_SHAPE, any |DM| above cdmt_dm_limit (its Eq. 2
                                 sweep is longer than the overlap, so wrap-around of the
                                 circular convolution would reach the kept samples,
                                 Sec. 2); 0: no such check (a deliberately short overlap) */
+    CDMT_OPT_FFT_SCHEDULE = 10 /* performance knob of the FP32 DM stage: 0 (default):
+                                at M_bin = 4096 with ndec in {1, 2, 4, 8} dividing
+                                n_d / 2, the backward FFT runs as radix 16 x 4 x 16 x 4
+                                with the two radix-4 digit exchanges done across lanes
+                                in registers (one LDS exchange per DM) and detection
+                                and downsampling in registers; other plans as 1.
+                                1: radix-16 stages with every digit exchange through
+                                LDS (all M_bin).  Same results up to FP32 rounding    */
 };
 
 /*

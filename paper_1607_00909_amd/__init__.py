@@ -24,7 +24,7 @@ CDMT_OK, CDMT_E_ARG, CDMT_E_SHAPE, CDMT_E_WORKSPACE, CDMT_E_DEVICE, CDMT_E_UNSUP
 # enum cdmt_opt
 CDMT_OPT_INPUT, CDMT_OPT_CHIRP_REF, CDMT_OPT_SIGN, CDMT_OPT_PRECISION, CDMT_OPT_DM_TILE, \
     CDMT_OPT_CHIRP_EXACT, CDMT_OPT_LANE_BINS, CDMT_OPT_FWD_N2, CDMT_OPT_OUT_LAYOUT, \
-    CDMT_OPT_DM_CHECK = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9
+    CDMT_OPT_DM_CHECK, CDMT_OPT_FFT_SCHEDULE = 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10
 LAYOUT_TIME_MAJOR, LAYOUT_CHANNEL_MAJOR = 0, 1
 INPUT_CF32, INPUT_CI8 = 0, 1
 CHIRP_CHANNEL, CHIRP_SUBBAND = 0, 1
@@ -316,7 +316,7 @@ def cdmt_incoherent(plan, nblock, fb, dm_coh, ddm0, ddm, ntrial, workspace, ws_b
                                   workspace, ws_bytes, out, stream), "cdmt_incoherent")
 
 
-_N_OPTIONS = 10
+_N_OPTIONS = 11
 
 
 def _snapshot(plan, workspace):
@@ -557,7 +557,7 @@ class Plan:
     def __init__(self, nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec, *,
                  input_kind=INPUT_CF32, chirp_ref=CHIRP_CHANNEL, sign=-1, dm_tile=None,
                  chirp_exact=None, lane_bins=None, fwd_n2=None, out_layout=None,
-                 dm_check=None):
+                 dm_check=None, fft_schedule=None):
         self.handle = cdmt_plan(nsub, f_centre_mhz, bw_sub_mhz, nfft, noverlap, nchan, ndec)
         self.nsub, self.nfft, self.noverlap, self.nchan, self.ndec = \
             nsub, nfft, noverlap, nchan, ndec
@@ -576,6 +576,8 @@ class Plan:
             cdmt_plan_set(self.handle, CDMT_OPT_OUT_LAYOUT, int(out_layout))
         if dm_check is not None:
             cdmt_plan_set(self.handle, CDMT_OPT_DM_CHECK, int(dm_check))
+        if fft_schedule is not None:
+            cdmt_plan_set(self.handle, CDMT_OPT_FFT_SCHEDULE, int(fft_schedule))
         self.input_kind = input_kind
 
     def __del__(self):

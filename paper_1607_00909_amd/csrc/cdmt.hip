@@ -275,6 +275,7 @@ struct FusedArgs {
     int chirp_ref;
     float sign;
     double f_centre, bw, delta, kk;   // MHz, MHz, bw/N MHz, 1e6 k_DM
+    int schedule;           // CDMT_OPT_FFT_SCHEDULE
 };
 
 struct DmList {
@@ -447,6 +448,305 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
     const int dt = rest % a.ndt;
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
     dm_item<M, R, RECUR>(a, ArgDms{dl}, dt, cg, sh);
+}
+
+// ---------------------------------------------------------------------------
+// DM stage at M_bin = 4096 with one LDS exchange per DM.
+//
+// The 4096-point backward transform is split as radix 16 x 4 x 16 x 4
+// (decimation in time: the stages take the input digits from the highest and
+// produce the output digits from the lowest).  Each of the 256 lanes of a
+// channel chunk holds 16 bin pairs in registers.  The two radix-4 stages take
+// their input bits from lane bits 4 and 5: v_permlane16_swap and
+// v_permlane32_swap transpose a register bit with lane bit 4 or 5 (a 2x2
+// transpose of a register pair across 16- or 32-lane halves, one instruction
+// per pair of values), so only the exchange before the second radix-16 stage
+// goes through LDS, and detection and downsampling run in registers.  Input
+// bits n0..n11, output bits m0..m11; register bits q0..q3, lane bits L0..L7
+// (L6, L7: the wave):
+//   load     regs n8..n11 (the bin's high digit), lanes L0-3 n0-n3, L4-5
+//            n6-n7, L6-7 n4-n5
+//   A        radix 16 over n8..n11 -> regs m0..m3
+//   permlane regs (m2, m3) <-> lanes (n6, n7)
+//   B        twiddle exp(2 pi i n67 m0..3 / 64), radix 4 over n6, n7 -> regs
+//            (m0, m1, m4, m5); lanes L4-5 = m2, m3
+//   LDS      regs <- n2..n5; lanes L0-3 = m0-m3, L4-5 = n0, n1, L6-7 = m4, m5
+//   C        twiddle exp(2 pi i n0..5 m0..5 / 4096), radix 16 over n2..n5 ->
+//            regs m6..m9
+//   permlane regs (m8, m9) <-> lanes (n0, n1)
+//   D        twiddle exp(2 pi i n01 m6..9 / 64) (the values of B), radix 4
+//            over n0, n1 -> regs (m6, m7, m10, m11); lanes L4-5 = m8, m9
+// Detection adds the two polarisations' power in registers; downsampling by
+// ndec = 2^K sums over m0..m(K-1), lane bits, across lanes (DPP).
+
+// exp(+2 pi i (q/4) ((q%4) + 4 l45) / 64) for lane bits (L4, L5) = l45, the
+// twiddles of stages B and D, [l45][q]; and exp(+2 pi i (l45 + 4 q) m / 4096)
+// for the six low output bits m, those of stage C, [m][l45][q].  Filled once
+// per device from double precision.
+__device__ __align__(16) float2 g_twB[4 * 16];
+__device__ __align__(16) float2 g_twC[64 * 4 * 16];
+
+// 2x2 transposes of (register pair, lane bit 4 / 5) for all four components
+__device__ __forceinline__ void perm16(cpair &a, cpair &b) {
+    const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    const auto z = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.z), __float_as_uint(b.z), false, false);
+    const auto w = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.w), __float_as_uint(b.w), false, false);
+    a = make_float4(__uint_as_float(x[0]), __uint_as_float(y[0]), __uint_as_float(z[0]), __uint_as_float(w[0]));
+    b = make_float4(__uint_as_float(x[1]), __uint_as_float(y[1]), __uint_as_float(z[1]), __uint_as_float(w[1]));
+}
+__device__ __forceinline__ void perm32(cpair &a, cpair &b) {
+    const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
+    const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
+    const auto z = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.z), __float_as_uint(b.z), false, false);
+    const auto w = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.w), __float_as_uint(b.w), false, false);
+    a = make_float4(__uint_as_float(x[0]), __uint_as_float(y[0]), __uint_as_float(z[0]), __uint_as_float(w[0]));
+    b = make_float4(__uint_as_float(x[1]), __uint_as_float(y[1]), __uint_as_float(z[1]), __uint_as_float(w[1]));
+}
+
+// register bits (q2, q3) <-> lane bits (L4, L5)
+__device__ __forceinline__ void swap_bits_q23_l45(cpair (&v)[16]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        if ((q & 4) == 0)
+            perm16(v[q], v[q + 4]);
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        perm32(v[q], v[q + 8]);
+}
+
+// twiddle then radix 4 over register bits (q2, q3), for each (q0, q1)
+__device__ __forceinline__ void radix4_q23(cpair (&v)[16], const float2 (&tw)[16]) {
+#pragma unroll
+    for (int q = 4; q < 16; ++q)
+        v[q] = cdmt::pmul(v[q], tw[q]);
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        cdmt::dft4<+1>(v[c], v[c + 4], v[c + 8], v[c + 12]);
+}
+
+// x from lane (lane xor the DPP pattern): quad_perm [1,0,3,2] = lane ^ 1,
+// [2,3,0,1] = lane ^ 2, row_half_mirror = lane ^ 7 within 8 lanes
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+constexpr int kDppX1 = 0xb1, kDppX2 = 0x4e, kDppX7 = 0x141;
+
+// One halving step of the sum across a lane pair (partner lane = DPP CTRL):
+// of every value pair (p[2j], p[2j+1]) this lane keeps index 2j + bit and
+// adds the partner's copy of it.
+template <int CTRL, int N>
+__device__ __forceinline__ void fold(const float (&p)[2 * N], float (&r)[N], bool bit) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float keep = bit ? p[2 * j + 1] : p[2 * j];
+        const float send = bit ? p[2 * j] : p[2 * j + 1];
+        r[j] = keep + dpp<CTRL>(send);
+    }
+}
+
+// One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
+// (K <= 3) and n_d / 2 a multiple of ndec.
+template <bool RECUR, int K, class DMS>
+__device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
+    constexpr int M = 4096;
+    const int L = threadIdx.x;
+    const int chunk = cg;
+    const int c = chunk % a.nchan;
+    const int bs = chunk / a.nchan;
+    const int s = bs % a.nsub;
+    const int b = bs / a.nsub;
+    const int l45 = (L >> 4) & 3;
+
+    // bins base + 256 q of this channel, both pols, increasing frequency
+    const int base = (L & 15) + 16 * (L >> 6) + 64 * l45;
+    cpair raw[16];
+    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M + base;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        raw[q] = src[256 * q];
+
+    // DM-independent part of Eq. 1 per bin (as in dm_item)
+    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
+    double nu0, off;
+    if (a.chirp_ref == 0) {
+        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
+        off = -0.5 * M;
+    } else {
+        nu0 = fs;
+        off = (double)c * M - 0.5 * a.n;
+    }
+    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
+    double g2[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const double nu = ((double)(base + 256 * q) + off) * a.delta;
+        g2[q] = scale * nu * nu / (nu0 + nu);
+    }
+
+    // twiddles of stages B and D (DM-invariant)
+    float2 twb[16];
+    {
+        const float4 *row = reinterpret_cast<const float4 *>(g_twB + 16 * l45);
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const float4 x = row[h];
+            twb[2 * h] = make_float2(x.x, x.y);
+            twb[2 * h + 1] = make_float2(x.z, x.w);
+        }
+    }
+    const float4 *rowc = reinterpret_cast<const float4 *>(
+        g_twC + 16 * (4 * ((L & 15) + 16 * (L >> 6)) + l45));
+
+    // LDS addresses of the exchange (in pairs), XOR-swizzled so that both the
+    // stores and the loads of 16 consecutive lanes hit 16 distinct 16-byte
+    // bank groups: element (regs after = n2..n5, lane after) at
+    // 256 q_after + (lane_after ^ ((n0 + 2 n1) + 4 (n2 + 2 n3)) on 4 bits)
+    int wa[4], ra[4];
+    {
+        const int wbase = 256 * (((L >> 2) & 3) + 4 * (L >> 6)) + 16 * (L & 3) +
+                          4 * (l45 ^ ((L >> 2) & 3));
+        const int rbase = (L & 0xf0) + ((L & 3) ^ l45);
+#pragma unroll
+        for (int c4 = 0; c4 < 4; ++c4) {
+            wa[c4] = wbase + (c4 ^ (L & 3));
+            ra[c4] = rbase + 4 * (((L >> 2) & 3) ^ c4);
+        }
+    }
+
+    // output: this lane's samples after the sum over the lane bits of
+    // m0..m(K-1); column of the channel in decreasing frequency
+    const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
+    const int d0 = dt * a.dm_tile;
+    const int d1 = min(a.ndm, d0 + a.dm_tile);
+
+    float2 step[16];
+    if constexpr (RECUR) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            raw[q] = cdmt::pmul(raw[q], cis_pi_f64(dms[d0] * g2[q]));
+            step[q] = cis_pi_f64(a.dm_step * g2[q]);
+        }
+    }
+
+    for (int d = d0; d < d1; ++d) {
+        cpair v[16];
+        if constexpr (RECUR) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                // swap halves per channel: bin i -> transform input (i + M/2) mod M
+                v[q ^ 8] = raw[q];
+                raw[q] = cdmt::pmul(raw[q], step[q]);
+            }
+        } else {
+            const double dm = dms[d];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const double t = dm * g2[q];
+                const double n = rint(t);
+                float sn, cs;
+                sincos_pi(static_cast<float>(t - n), sn, cs);
+                const int flip = static_cast<int>(n) << 31;
+                sn = __int_as_float(__float_as_int(sn) ^ flip);
+                cs = __int_as_float(__float_as_int(cs) ^ flip);
+                v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, sn));
+            }
+        }
+        // A
+        cdmt::dft16<+1>(v);
+        // B
+        swap_bits_q23_l45(v);
+        radix4_q23(v, twb);
+        // stage C's twiddles, fetched across the exchange
+        float2 twc[16];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const float4 x = rowc[h];
+            twc[2 * h] = make_float2(x.x, x.y);
+            twc[2 * h + 1] = make_float2(x.z, x.w);
+        }
+        // LDS exchange: the previous DM's loads are done before any store
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            sh[wa[q & 3] + 64 * (q >> 2)] = v[q];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = sh[ra[q & 3] + 256 * q];
+        // C
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+            v[q] = cdmt::pmul(v[q], twc[q]);
+        cdmt::dft16<+1>(v);
+        // D
+        swap_bits_q23_l45(v);
+        radix4_q23(v, twb);
+
+        // detection: registers (m6, m7, m10, m11); lanes L0-3 m0-m3, L4-5
+        // m8, m9, L6-7 m4, m5
+        float p[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const cpair y = v[q];
+            p[q] = y.x * y.x + y.y * y.y + y.z * y.z + y.w * y.w;
+        }
+        const bool b0 = L & 1, b1 = (L >> 1) & 1, b2 = (L >> 2) & 1;
+        // sum over m0..m(K-1): remaining value r is register q(r) with
+        //   K = 0: q = r; K = 1: q = 2 r + L0; K = 2: q = 4 r + 2 L1 + L0;
+        //   K = 3: q = 8 r + 4 L1 + 2 L0 + L2
+        constexpr int NR = 16 >> K;
+        float o[NR];
+        if constexpr (K == 0) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                o[r] = p[r];
+        } else if constexpr (K == 1) {
+            fold<kDppX1, 8>(p, o, b0);
+        } else if constexpr (K == 2) {
+            float p1[8];
+            fold<kDppX1, 8>(p, p1, b0);
+            fold<kDppX2, 4>(p1, o, b1);
+        } else {
+            float p1[8], p2[4];
+            fold<kDppX7, 8>(p, p1, b2);
+            fold<kDppX1, 4>(p1, p2, b0);
+            fold<kDppX2, 2>(p2, o, b1);
+        }
+        // sample index m of the first summed sample of value r, then the
+        // filterbank sample (m - n_d / 2) / ndec if it is kept
+        const int mlane = (K <= 0 ? (L & 1) : 0) + (K <= 1 ? 2 * ((L >> 1) & 1) : 0) +
+                          (K <= 2 ? 4 * ((L >> 2) & 1) : 0) + 8 * ((L >> 3) & 1) +
+                          16 * ((L >> 6) & 1) + 32 * (L >> 7) + 256 * ((L >> 4) & 1) +
+                          512 * ((L >> 5) & 1);
+        float *out = a.out + (long long)d * a.ntime_out * a.nch_out +
+                     (long long)b * a.tblk * a.t_stride + col * a.col_stride;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            int q;
+            if constexpr (K == 0) q = r;
+            else if constexpr (K == 1) q = 2 * r + (L & 1);
+            else if constexpr (K == 2) q = 4 * r + 2 * ((L >> 1) & 1) + (L & 1);
+            else q = 8 * r + 4 * ((L >> 1) & 1) + 2 * (L & 1) + ((L >> 2) & 1);
+            const int m = mlane + 64 * (q & 1) + 128 * ((q >> 1) & 1) + 1024 * ((q >> 2) & 1) +
+                          2048 * (q >> 3);
+            const int tq = (m - a.nd_half) >> K;
+            if (m >= a.nd_half && tq < a.tblk)
+                out[(long long)tq * a.t_stride] = o[r];
+        }
+    }
+}
+
+template <bool RECUR, int K>
+__global__ __launch_bounds__(256, 2) void fused_dedisperse_p(FusedArgs a, DmList dl) {
+    __shared__ cpair sh[4096];
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int ci = lw % a.inner;
+    const int rest = lw / a.inner;
+    const int dt = rest % a.ndt;
+    const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
+    dm_item_p<RECUR, K>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1160,19 +1460,24 @@ struct BatchBeam {
 };
 
 constexpr int kBatchQueues = 8;
+// launch groups: 7 M_bin x 2 transfer-function forms, plus the lane-swap
+// item's 4 downsampling factors x 2 forms at M_bin = 4096
+constexpr int kBatchGroups = 22;
 
 __global__ void batch_reset(unsigned long long *ctr, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
         ctr[i] = 0;
 }
 
-template <int M, bool RECUR>
+// K >= 0: the M_bin = 4096 lane-swap item (dm_item_p) with ndec = 2^K
+template <int M, bool RECUR, int K = -1>
 __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__ beams, int nbeam,
                                                    long long total,
                                                    unsigned long long *__restrict__ ctr) {
     using Sh = FusedShape<M, 16>;
     static_assert(Sh::WG == 256, "batched launches use 256-lane workgroups");
-    __shared__ cpair sh[Sh::C * Sh::STRIDE];
+    static_assert(K < 0 || M == 4096, "the lane-swap item is built for M_bin = 4096");
+    __shared__ cpair sh[K >= 0 ? 4096 : Sh::C * Sh::STRIDE];
     __shared__ long long s_item;
     const int q = blockIdx.x % kBatchQueues;
     const long long lo = total * q / kBatchQueues;
@@ -1198,7 +1503,10 @@ __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__
         const long long rest = local / a.inner;
         const int dt = (int)(rest % a.ndt);
         const int cg = (int)((rest / a.ndt) * a.inner + ci);
-        dm_item<M, 16, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
+        if constexpr (K >= 0)
+            dm_item_p<RECUR, K>(a, MemDms{beams[b].dms}, dt, cg, sh);
+        else
+            dm_item<M, 16, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
     }
 }
 
@@ -1247,6 +1555,27 @@ int ensure_twiddles() {
     }
     if (hipMemcpyToSymbol(HIP_SYMBOL(cdmt::g_stage_tw), st.data(),
                           sizeof(float2) * st.size()) != hipSuccess)
+        return CDMT_E_DEVICE;
+    // the M_bin = 4096 lane-swap schedule: stages B and D [l45][q], stage C
+    // [m][l45][q]
+    std::vector<float2> tb(4 * 16), tc(64 * 4 * 16);
+    for (int l45 = 0; l45 < 4; ++l45)
+        for (int q = 0; q < 16; ++q) {
+            const long long e = (long long)(q >> 2) * ((q & 3) + 4 * l45);
+            const double ang = 2.0 * M_PI * ((double)(e % 64) / 64.0);
+            tb[16 * l45 + q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
+    for (int mm = 0; mm < 64; ++mm)
+        for (int l45 = 0; l45 < 4; ++l45)
+            for (int q = 0; q < 16; ++q) {
+                const long long e = (long long)(l45 + 4 * q) * mm;
+                const double ang = 2.0 * M_PI * ((double)(e % 4096) / 4096.0);
+                tc[16 * (4 * mm + l45) + q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+            }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_twB), tb.data(), sizeof(float2) * tb.size()) !=
+            hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(g_twC), tc.data(), sizeof(float2) * tc.size()) !=
+            hipSuccess)
         return CDMT_E_DEVICE;
     g_init_done[dev] = 1;
     return CDMT_OK;
@@ -1322,6 +1651,33 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
 
 
 
+// The M_bin = 4096 lane-swap schedule sums ndec = 2^K samples across lanes
+// aligned to multiples of ndec: K for this launch, or -1 when the plan needs
+// the general kernel (other ndec, n_d / 2 not a multiple of ndec, or the
+// schedule switched off).
+int lane_swap_k(const FusedArgs &a) {
+    if (a.schedule != 0)
+        return -1;
+    for (int k = 0; k <= 3; ++k)
+        if (a.ndec == (1 << k))
+            return a.nd_half % a.ndec == 0 ? k : -1;
+    return -1;
+}
+
+void launch_p(bool recur, int k, int grid, const FusedArgs &a, const DmList &dl,
+              hipStream_t st) {
+    switch (k + (recur ? 4 : 0)) {
+    case 0: fused_dedisperse_p<false, 0><<<grid, 256, 0, st>>>(a, dl); break;
+    case 1: fused_dedisperse_p<false, 1><<<grid, 256, 0, st>>>(a, dl); break;
+    case 2: fused_dedisperse_p<false, 2><<<grid, 256, 0, st>>>(a, dl); break;
+    case 3: fused_dedisperse_p<false, 3><<<grid, 256, 0, st>>>(a, dl); break;
+    case 4: fused_dedisperse_p<true, 0><<<grid, 256, 0, st>>>(a, dl); break;
+    case 5: fused_dedisperse_p<true, 1><<<grid, 256, 0, st>>>(a, dl); break;
+    case 6: fused_dedisperse_p<true, 2><<<grid, 256, 0, st>>>(a, dl); break;
+    default: fused_dedisperse_p<true, 3><<<grid, 256, 0, st>>>(a, dl); break;
+    }
+}
+
 // A dispatch covers at most 2^32 - 1 work-items, so large jobs are split into
 // several launches: by DM (at most kMaxDmPerLaunch per launch, passed by
 // value) and, when the grid would still be too large, by chunk groups.
@@ -1361,6 +1717,8 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
                     fused_dedisperse_mx<true, BF><<<grid, WG, 0, st>>>(a, dl);
                 else
                     fused_dedisperse_mx<false, BF><<<grid, WG, 0, st>>>(a, dl);
+            } else if (M == 4096 && R == 16 && lane_swap_k(a) >= 0) {
+                launch_p(recur, lane_swap_k(a), grid, a, dl, st);
             } else {
                 if (recur)
                     fused_dedisperse<M, R, true><<<grid, WG, 0, st>>>(a, dl);
@@ -1397,6 +1755,7 @@ FusedArgs fused_args(const cdmt_plan_s *p, void *ws, int nblock, float *out) {
     a.bw = p->bw;
     a.delta = p->bw / p->nfft;
     a.kk = 1e6 * kKdm;
+    a.schedule = p->fft_schedule;
     // recurrence allowed when every DM sits on the progression to within a
     // phase error of 1e-7 half-cycles (dm_step carries the tolerance here)
     a.dm_step = p->chirp_exact ? 0.0 : 1e-7 / max_half_cycles_per_dm(p);
@@ -1642,8 +2001,8 @@ struct cdmt_batch_s {
     int wg_per_cu = 2;
     long long total = 0;                      // work items over all launches
     struct Launch {
-        int m, recur, first, count;           // M_bin, form, table rows [first, first + count)
-        long long items;
+        int m, recur, k, first, count;        // M_bin, form, lane-swap K (-1: none),
+        long long items;                      // table rows [first, first + count)
     };
     std::vector<Launch> launches;             // one persistent launch per (M_bin, form)
     hipGraph_t graph = nullptr;
@@ -1688,7 +2047,7 @@ int batch_layout(const cdmt_beam_t *beams, int nbeam, std::vector<size_t> *spec_
     *tab_off = off;
     off = align256(off + (size_t)nbeam * sizeof(BatchBeam));
     *ctr_off = off;
-    *total = off + 14 * kBatchQueues * sizeof(unsigned long long);  // 7 M_bin x 2 forms
+    *total = off + kBatchGroups * kBatchQueues * sizeof(unsigned long long);
     return CDMT_OK;
 }
 
@@ -1706,7 +2065,7 @@ int batch_upload(cdmt_batch_s *bt) {
     bt->launches.clear();
     bt->total = 0;
     std::vector<BatchBeam> rows(nbeam);
-    std::vector<int> rec(nbeam);
+    std::vector<int> rec(nbeam), kk(nbeam);
     for (int b = 0; b < nbeam; ++b) {
         const cdmt_beam_t &B = bt->beams[b];
         const cdmt_plan_s *p = B.plan;
@@ -1723,13 +2082,15 @@ int batch_upload(cdmt_batch_s *bt) {
                            arithmetic(d.data(), B.ndm, T.a.dm_step);
         T.a.dm_step = recur ? d[1] - d[0] : 0.0;
         rec[b] = recur ? 1 : 0;
+        kk[b] = p->m == 4096 ? lane_swap_k(T.a) : -1;
         T.dms = reinterpret_cast<const double *>(bt->ws + bt->dm_off) + dm_at[b];
     }
     for (int m = 64; m <= 4096; m *= 2) {
         for (int r = 1; r >= 0; --r) {
-            cdmt_batch_s::Launch L{m, r, (int)tab.size(), 0, 0};
+          for (int k = -1; k <= (m == 4096 ? 3 : -1); ++k) {
+            cdmt_batch_s::Launch L{m, r, k, (int)tab.size(), 0, 0};
             for (int b = 0; b < nbeam; ++b) {
-                if (bt->beams[b].plan->m != m || rec[b] != r)
+                if (bt->beams[b].plan->m != m || rec[b] != r || kk[b] != k)
                     continue;
                 BatchBeam T = rows[b];
                 const int C = 4096 / m;
@@ -1742,6 +2103,7 @@ int batch_upload(cdmt_batch_s *bt) {
                 bt->launches.push_back(L);
                 bt->total += L.items;
             }
+          }
         }
     }
     if (hipMemcpy(bt->ws + bt->dm_off, dmall.data(), dmall.size() * sizeof(double),
@@ -1763,6 +2125,20 @@ void batch_launch(int recur, const BatchBeam *tab, int count, long long items,
         dm_batch<M, false><<<grid, 256, 0, st>>>(tab, count, items, ctr);
 }
 
+void batch_launch_p(int recur, int k, const BatchBeam *tab, int count, long long items,
+                    unsigned long long *ctr, int grid, hipStream_t st) {
+    switch (k + (recur ? 4 : 0)) {
+    case 0: dm_batch<4096, false, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 1: dm_batch<4096, false, 1><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 2: dm_batch<4096, false, 2><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 3: dm_batch<4096, false, 3><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 4: dm_batch<4096, true, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 5: dm_batch<4096, true, 1><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 6: dm_batch<4096, true, 2><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    default: dm_batch<4096, true, 3><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    }
+}
+
 // forward stage of beam b with the batch's split for it
 int batch_forward(cdmt_batch_s *bt, int b, hipStream_t st) {
     const cdmt_beam_t &B = bt->beams[b];
@@ -1781,7 +2157,7 @@ int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
             return r;
     }
     unsigned long long *ctr = reinterpret_cast<unsigned long long *>(bt->ws + bt->ctr_off);
-    batch_reset<<<1, 128, 0, st>>>(ctr, 14 * kBatchQueues);
+    batch_reset<<<1, 128, 0, st>>>(ctr, kBatchGroups * kBatchQueues);
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, bt->device) !=
         hipSuccess || ncu < 1)
@@ -1792,6 +2168,12 @@ int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
         const cdmt_batch_s::Launch &L = bt->launches[k];
         unsigned long long *c = ctr + k * kBatchQueues;
         const BatchBeam *t = tab + L.first;
+        if (L.k >= 0) {
+            batch_launch_p(L.recur, L.k, t, L.count, L.items, c, grid, st);
+            if (hipGetLastError() != hipSuccess)
+                return CDMT_E_DEVICE;
+            continue;
+        }
         switch (L.m) {
         case 64: batch_launch<64>(L.recur, t, L.count, L.items, c, grid, st); break;
         case 128: batch_launch<128>(L.recur, t, L.count, L.items, c, grid, st); break;

@@ -204,6 +204,11 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
             return CDMT_E_ARG;
         p->dm_check = value;
         return CDMT_OK;
+    case CDMT_OPT_FFT_SCHEDULE:
+        if (value != 0 && value != 1)
+            return CDMT_E_ARG;
+        p->fft_schedule = value;
+        return CDMT_OK;
     default:
         return CDMT_E_ARG;
     }
@@ -223,6 +228,7 @@ int cdmt_plan_get(cdmt_plan_t p, int opt, int *value) {
     case CDMT_OPT_FWD_N2: *value = p->n2; return CDMT_OK;
     case CDMT_OPT_OUT_LAYOUT: *value = p->out_layout; return CDMT_OK;
     case CDMT_OPT_DM_CHECK: *value = p->dm_check; return CDMT_OK;
+    case CDMT_OPT_FFT_SCHEDULE: *value = p->fft_schedule; return CDMT_OK;
     default: return CDMT_E_ARG;
     }
 }

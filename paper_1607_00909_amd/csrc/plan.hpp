@@ -14,6 +14,7 @@ struct cdmt_plan_s {
     int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 16, chirp_exact = 0, lane_bins = 16;
     int out_layout = 0;     // 0: filterbanks [DM][t][ch], 1: [DM][ch][t]
     int dm_check = 1;       // 1: reject DMs whose Eq. 2 sweep exceeds the overlap
+    int fft_schedule = 0;   // DM-stage transform schedule (CDMT_OPT_FFT_SCHEDULE)
     int m, nd, tblk, n1, n2;
 };
 

@@ -180,6 +180,15 @@ def pulse_draws(w: Workload, seed: int | None = None):
     return out
 
 
+def candidate_draws(n: int = 64, seed: int = 1607, lo: float = 5.0, hi: float = 60.0):
+    """Refinement candidates: (true DM, pulse output sample, noise seed) with
+    the DM uniform in [lo, hi) (continuous, off the trial grid) and the
+    output sample in the middle block of a 4-block segment."""
+    g = np.random.default_rng(np.random.SeedSequence([seed, 4711]))
+    return [(float(g.uniform(lo, hi)), int(g.integers(0, 1 << 30)),
+             int(g.integers(0, 1 << 30))) for _ in range(n)]
+
+
 def device_noise(kind: str, nsub: int, ntime: int, sigma: float, seed: int, device):
     """Large noise generated directly in device memory with torch's seeded
     generator (for workloads too big to build on the host): a torch tensor

@@ -91,8 +91,10 @@ def test_batch_matches_single_beams_and_oracle(hip_lib):
     print("[gpu-case] batch of 5 beams, eager", flush=True)
     beams, host = _setup(hip_lib, torch, SPECS)
     batch = hip_lib.Batch(beams)
-    # M 4096 (two beams), 2048, 512 with the recurrence; M 1024 exact
-    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == 4
+    # M 4096 with the recurrence, ndec 8 and ndec 4 (the lane-swap item is
+    # built per downsampling factor); M 2048 and 512 with the recurrence;
+    # M 1024 exact
+    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == 5
     batch.run()
     torch.cuda.synchronize()
     for i, (sp, (plan, nblock, x, dms, out)) in enumerate(zip(SPECS, beams)):

@@ -377,3 +377,105 @@ def test_dm_gradient_at_full_size_on_sampled_pairs(hip_lib):
     print(f"full-size gradient vs oracle (2 pairs x 64 DMs): worst error / sum|terms| "
           f"{(err / absum).max():.2e} (bar {bar(w.nfft, w.nchan):.2e})", flush=True)
     assert np.all(err <= bar(w.nfft, w.nchan) * absum)
+
+
+@pytest.mark.parametrize("cand", [0, 1])
+def test_refinement_of_a_candidate_at_full_size(hip_lib, cand):
+    """A candidate of the refinement workload at full size: its own ~1 s
+    segment (4 blocks of N_bin 65536) of 288 subbands, complex float32 noise
+    sigma 1, a pulse injected by the oracle (inverse transfer function, nu0 per
+    subband) at a random continuous DM.  From the nearest trial of the 0.5-step
+    coarse grid, gradient ascent on the S/N of the channel-summed series finds
+    the DM to within 0.02 pc cm^-3; at the coarse trial, d(S/N)/dDM from the
+    autograd function matches central differences (step 1e-4 pc cm^-3) of the
+    oracle's FP64 S/N over the whole segment; and the DM gradient of a loss on
+    two sampled (subband, block) pairs, one holding the pulse, matches the
+    oracle's within the module's rounding bound."""
+    torch = _torch()
+    import ctypes
+    w = synth.LOFAR
+    nblock = 4
+    dm_true, r_t, seed = synth.candidate_draws(64)[cand]
+    cfg = oracle.Config(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                        chirp_ref=oracle.SUBBAND)
+    t0 = cfg.tblk + r_t % (2 * cfg.tblk)
+    print(f"[gpu-case] full-size refinement, candidate {cand}: DM {dm_true:.4f}, t0 {t0}",
+          flush=True)
+    x = synth.gaussian_voltages(w.nsub, cfg.ntime_in(nblock), 1.0, seed)
+    for s in range(w.nsub):
+        oracle.inject_impulse(cfg, x, s, dm_true, oracle.pulse_sample(cfg, t0), 90.0)
+    v = synth.encode_cf32(x)
+    del x
+    plan = hip_lib.Plan(w.nsub, w.f_centre, w.bw, w.nfft, w.noverlap, w.nchan, w.ndec,
+                        chirp_ref=hip_lib.CHIRP_SUBBAND, chirp_exact=1)
+    ws = plan.workspace(nblock)
+    xd = torch.from_numpy(v).cuda()
+    plan.forward(xd, nblock, ws)
+    dm_c = round(dm_true * 2.0) / 2.0
+    with torch.no_grad():
+        f0 = hip_lib.dedisperse_dm(plan, torch.tensor([dm_c], dtype=torch.float64), nblock, ws)
+        tpk = int(f0[0].double().sum(dim=1).argmax())
+    assert tpk == t0
+
+    def snr_grad(dm):
+        d = torch.tensor([dm], dtype=torch.float64, requires_grad=True)
+        F = hip_lib.dedisperse_dm(plan, d, nblock, ws)
+        sr = F[0].double().sum(dim=1)
+        snr = (sr[tpk] - sr.mean()) / sr.std(correction=0)
+        snr.backward()
+        return float(snr.detach()), float(d.grad[0])
+
+    # d(S/N)/dDM at the coarse trial against the oracle's central differences
+    h = 1e-4
+    S0, g0 = snr_grad(dm_c)
+    Sp = _snr_np(oracle.dedisperse(cfg, v, nblock, [dm_c + h])[0], tpk)
+    Sm = _snr_np(oracle.dedisperse(cfg, v, nblock, [dm_c - h])[0], tpk)
+    fd = (Sp - Sm) / (2 * h)
+    print(f"coarse DM {dm_c}: S/N {S0:.5f}, d(S/N)/dDM autograd {g0:.6e}, oracle differences "
+          f"{fd:.6e}", flush=True)
+    assert abs(g0 - fd) <= 1e-3 * abs(fd)
+
+    # gradient ascent from the coarse trial
+    dm, S, g = dm_c, S0, g0
+    step = 0.25 / abs(g)
+    for it in range(40):
+        cand_dm = dm + step * g
+        Sc, gc = snr_grad(cand_dm)
+        if Sc > S:
+            dm, S, g = cand_dm, Sc, gc
+            step *= 1.5
+        else:
+            step *= 0.3
+        if abs(step * g) < 1e-4:
+            break
+    print(f"refined DM {dm:.5f} (true {dm_true:.5f}, coarse {dm_c}) after {it + 1} steps, "
+          f"S/N {S0:.3f} -> {S:.3f}", flush=True)
+    assert abs(dm - dm_true) <= 0.02
+    assert S > S0 or abs(dm_c - dm_true) < 0.02
+
+    # the DM gradient on two sampled pairs (the pulse's block and another)
+    r = np.random.default_rng(31 + cand)
+    _, ntout, nch = plan.shape(nblock)
+    G = torch.zeros((1, ntout, nch), dtype=torch.float32, device="cuda")
+    total, absum = np.zeros(1), np.zeros(1)
+    for s, b in ((41, t0 // cfg.tblk), (250, 3)):
+        cols = [(w.nsub - 1 - s) * w.nchan + (w.nchan - 1 - c) for c in range(w.nchan)]
+        gb = r.standard_normal((1, cfg.tblk, w.nchan)).astype(np.float32)
+        G[:, b * cfg.tblk:(b + 1) * cfg.tblk, cols] = torch.from_numpy(gb).cuda()
+        c1 = oracle.Config(1, cfg.sub_centre(s), cfg.bw, cfg.nfft, cfg.noverlap, cfg.nchan,
+                           cfg.ndec, chirp_ref=oracle.SUBBAND)
+        gg, a = oracle.dm_gradient(c1, v[s:s + 1], 0, b, [dm], gb.astype(np.float64),
+                                   with_abs=True)
+        total += gg
+        absum += a
+    n = hip_lib.cdmt_gradient_workspace_size(plan.handle, nblock, 1)
+    gws = torch.empty(max(1, n), dtype=torch.uint8, device="cuda")
+    dldm = torch.empty(1, dtype=torch.float64, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    hip_lib.cdmt_dm_gradient(plan.handle, P(ws), ws.numel(), nblock, [dm], P(G), P(gws),
+                             gws.numel(), P(dldm), None)
+    torch.cuda.synchronize()
+    err = abs(float(dldm.cpu()[0]) - total[0])
+    print(f"sampled-pair gradient at the refined DM: error / sum|terms| {err / absum[0]:.2e} "
+          f"(bar {bar(w.nfft, w.nchan):.2e})", flush=True)
+    assert err <= bar(w.nfft, w.nchan) * absum[0]
