@@ -209,6 +209,28 @@ int cdmt_dm_gradient(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nbl
                      size_t gws_bytes, double *dldm, void *hip_stream);
 
 /*
+ * cdmt_dm_gradient for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same result, bit for bit, with the FP64 partial sums kept in a scratch
+ * array the library holds on each GPU (cdmt_noalloc_scratch_bytes() =
+ * 16 MiB, held from the first call on that GPU until the process ends)
+ * instead of the caller's gws.  The caller still passes the spectra
+ * workspace, grad_out and dldm.  Limit: cdmt_gradient_workspace_size(plan,
+ * nblock, ndm) must not exceed the scratch size (CDMT_E_WORKSPACE
+ * otherwise, nothing written), e.g. 64 DMs over 288 subbands x 4 blocks x
+ * 16 channels at M_bin = 4096 use 9.4 MB.  Every call on a GPU shares that
+ * GPU's array and overwrites the slots it uses before reading them, so
+ * nothing needs clearing; calls that overlap on one GPU (other streams or
+ * threads) race on it and must be serialised by the caller.  The first call
+ * on a device also sets up the library's per-device tables (synchronous
+ * copies, no allocation).  Other rules as cdmt_dm_gradient.
+ */
+int cdmt_dm_gradient_noalloc(cdmt_plan_t plan, void *workspace, size_t ws_bytes, int nblock,
+                             const double *dm_list, int ndm, const float *grad_out, double *dldm,
+                             void *hip_stream);
+size_t cdmt_noalloc_scratch_bytes(void);
+
+/*
  * Gradient of the same kind of loss with respect to the voltages, for one DM
  * (call once per DM with accumulate = 1 to sum over DMs): the adjoint
  * continued through the transfer function and the forward stage (forward

@@ -37,7 +37,8 @@ EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for", "
            "cdmt_batch_workspace_size", "cdmt_batch_create", "cdmt_batch_set", "cdmt_batch_get",
            "cdmt_batch_run", "cdmt_batch_run_graph", "cdmt_batch_autotune", "cdmt_batch_destroy",
            "cdmt_batch_beam_set", "cdmt_batch_beam_get",
-           "cdmt_gradient_workspace_size", "cdmt_dm_gradient",
+           "cdmt_gradient_workspace_size", "cdmt_dm_gradient", "cdmt_dm_gradient_noalloc",
+           "cdmt_noalloc_scratch_bytes",
            "cdmt_voltage_gradient_workspace_size", "cdmt_voltage_gradient",
            "cdmt_incoherent_shape", "cdmt_incoherent_workspace_size", "cdmt_incoherent")
 # enum cdmt_batch_opt
@@ -98,6 +99,9 @@ def load():
         lib.cdmt_redigitise.argtypes = [P, I, LL, I, F, F, P, Z, P, P, P, P]
         lib.cdmt_gradient_workspace_size.argtypes = [P, I, I, ctypes.POINTER(Z)]
         lib.cdmt_dm_gradient.argtypes = [P, P, Z, I, ctypes.POINTER(D), I, P, P, Z, P, P]
+        lib.cdmt_dm_gradient_noalloc.argtypes = [P, P, Z, I, ctypes.POINTER(D), I, P, P, P]
+        lib.cdmt_noalloc_scratch_bytes.argtypes = []
+        lib.cdmt_noalloc_scratch_bytes.restype = Z
         lib.cdmt_voltage_gradient_workspace_size.argtypes = [P, I, ctypes.POINTER(Z)]
         lib.cdmt_voltage_gradient.argtypes = [P, P, Z, I, D, P, P, Z, P, I, P]
         lib.cdmt_incoherent_shape.argtypes = [P, I, ctypes.POINTER(D), I, D, D, I,
@@ -278,6 +282,17 @@ def cdmt_dm_gradient(plan, workspace, ws_bytes, nblock, dms, grad_out, gws, gws_
     arr, n = _dm_array(dms)
     _check(load().cdmt_dm_gradient(plan, workspace, ws_bytes, nblock, arr, n, grad_out, gws,
                                    gws_bytes, dldm, stream), "cdmt_dm_gradient")
+
+
+def cdmt_dm_gradient_noalloc(plan, workspace, ws_bytes, nblock, dms, grad_out, dldm,
+                             stream) -> None:
+    arr, n = _dm_array(dms)
+    _check(load().cdmt_dm_gradient_noalloc(plan, workspace, ws_bytes, nblock, arr, n, grad_out,
+                                           dldm, stream), "cdmt_dm_gradient_noalloc")
+
+
+def cdmt_noalloc_scratch_bytes() -> int:
+    return int(load().cdmt_noalloc_scratch_bytes())
 
 
 def cdmt_voltage_gradient_workspace_size(plan, nblock) -> int:

@@ -1516,15 +1516,30 @@ __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__
 std::mutex g_init_mu;
 std::vector<char> g_init_done;   // per device
 
+// Library-owned scratch of cdmt_dm_gradient_noalloc: the FP64 partial sums
+// that cdmt_dm_gradient keeps in the caller's gradient workspace.  Each GPU
+// holds its own copy until the process ends.  Host code never names the
+// array itself (on the host the name is only a stand-in): it uses the device
+// address fetched once per device in ensure_twiddles.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+std::vector<void *> g_scratch_ptr;   // per device, from hipGetSymbolAddress
+
 int ensure_twiddles() {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess)
         return CDMT_E_DEVICE;
     std::lock_guard<std::mutex> lk(g_init_mu);
-    if ((int)g_init_done.size() <= dev)
+    if ((int)g_init_done.size() <= dev) {
         g_init_done.resize(dev + 1, 0);
+        g_scratch_ptr.resize(dev + 1, nullptr);
+    }
     if (g_init_done[dev])
         return CDMT_OK;
+    void *sp = nullptr;
+    if (hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch)) != hipSuccess || !sp)
+        return CDMT_E_DEVICE;
+    g_scratch_ptr[dev] = sp;
     std::vector<float2> h(kTwiddleEntries);
     h[0] = make_float2(1.f, 0.f);
     for (int p = 1; p < kTwiddleEntries; p <<= 1) {
@@ -1832,6 +1847,54 @@ int launch_dv_m(const FusedArgs &a0, double dm, const float *gout, cpair *gin, l
 }
 
 
+// cdmt_dm_gradient with the partial sums in the caller's workspace gws, or
+// (use_scratch) in this device's library-owned scratch array.
+int dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const double *dm_list,
+                int ndm, const float *grad_out, void *gws, size_t gws_bytes, bool use_scratch,
+                double *dldm, void *hip_stream) {
+    int st = check_call(p, ws, ws_bytes, nblock);
+    if (st)
+        return st;
+    if (ndm < 0)
+        return CDMT_E_ARG;
+    if (p->m > 4096)
+        return CDMT_E_UNSUPPORTED;
+    if (ndm == 0 || nblock == 0)
+        return CDMT_OK;
+    if (!dm_list || !grad_out || (!use_scratch && !gws) || !dldm)
+        return CDMT_E_ARG;
+    if ((st = check_dms(p, dm_list, ndm)))
+        return st;
+    size_t need = 0;
+    cdmt_gradient_workspace_size(p, nblock, ndm, &need);
+    if (gws_bytes < need)
+        return CDMT_E_WORKSPACE;
+    if ((st = ensure_twiddles()))
+        return st;
+    if (use_scratch) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess)
+            return CDMT_E_DEVICE;
+        std::lock_guard<std::mutex> lk(g_init_mu);
+        gws = g_scratch_ptr[dev];
+    }
+    const FusedArgs a = fused_args(p, ws, nblock, nullptr);
+    const long long ncg = grad_groups(p, nblock);
+    double *part = static_cast<double *>(gws);
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    switch (p->m) {
+    case 64: return launch_grad_m<64>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 128: return launch_grad_m<128>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 256: return launch_grad_m<256>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 512: return launch_grad_m<512>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 1024: return launch_grad_m<1024>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 2048: return launch_grad_m<2048>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    case 4096: return launch_grad_m<4096>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
+    default: return CDMT_E_UNSUPPORTED;
+    }
+}
+
+
 }  // namespace
 
 extern "C" {
@@ -1891,40 +1954,20 @@ int cdmt_dedisperse(cdmt_plan_t p, void *ws, size_t ws_bytes, const void *voltag
 int cdmt_dm_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, const double *dm_list,
                      int ndm, const float *grad_out, void *gws, size_t gws_bytes, double *dldm,
                      void *hip_stream) {
-    int st = check_call(p, ws, ws_bytes, nblock);
-    if (st)
-        return st;
-    if (ndm < 0)
-        return CDMT_E_ARG;
-    if (p->m > 4096)
-        return CDMT_E_UNSUPPORTED;
-    if (ndm == 0 || nblock == 0)
-        return CDMT_OK;
-    if (!dm_list || !grad_out || !gws || !dldm)
-        return CDMT_E_ARG;
-    if ((st = check_dms(p, dm_list, ndm)))
-        return st;
-    size_t need = 0;
-    cdmt_gradient_workspace_size(p, nblock, ndm, &need);
-    if (gws_bytes < need)
-        return CDMT_E_WORKSPACE;
-    if ((st = ensure_twiddles()))
-        return st;
-    const FusedArgs a = fused_args(p, ws, nblock, nullptr);
-    const long long ncg = grad_groups(p, nblock);
-    double *part = static_cast<double *>(gws);
-    hipStream_t s = static_cast<hipStream_t>(hip_stream);
-    switch (p->m) {
-    case 64: return launch_grad_m<64>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    case 128: return launch_grad_m<128>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    case 256: return launch_grad_m<256>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    case 512: return launch_grad_m<512>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    case 1024: return launch_grad_m<1024>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    case 2048: return launch_grad_m<2048>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    case 4096: return launch_grad_m<4096>(a, dm_list, ndm, grad_out, part, ncg, dldm, s);
-    default: return CDMT_E_UNSUPPORTED;
-    }
+    return dm_gradient(p, ws, ws_bytes, nblock, dm_list, ndm, grad_out, gws, gws_bytes, false, dldm,
+                       hip_stream);
 }
+
+
+int cdmt_dm_gradient_noalloc(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock,
+                             const double *dm_list, int ndm, const float *grad_out, double *dldm,
+                             void *hip_stream) {
+    return dm_gradient(p, ws, ws_bytes, nblock, dm_list, ndm, grad_out, nullptr, kScratchBytes, true,
+                       dldm, hip_stream);
+}
+
+
+size_t cdmt_noalloc_scratch_bytes(void) { return kScratchBytes; }
 
 
 int cdmt_voltage_gradient(cdmt_plan_t p, void *ws, size_t ws_bytes, int nblock, double dm,

@@ -23,7 +23,7 @@ def lib():
 
 def _declared():
     src = open(os.path.join(ROOT, "include", "cdmt.h")).read()
-    return set(re.findall(r"^\s*(?:int|void|const char \*)\s*(cdmt_\w+)\s*\(", src, re.M))
+    return set(re.findall(r"^\s*(?:int|void|size_t|const char \*)\s*(cdmt_\w+)\s*\(", src, re.M))
 
 
 def test_header_and_binding_agree():
