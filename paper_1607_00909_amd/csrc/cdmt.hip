@@ -451,79 +451,45 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
 }
 
 // ---------------------------------------------------------------------------
-// DM stage at M_bin = 4096 with one LDS exchange per DM.
+// DM stage at M_bin = 4096: three radix-16 passes, two LDS exchanges per DM.
 //
-// The 4096-point backward transform is split as radix 16 x 4 x 16 x 4
-// (decimation in time: the stages take the input digits from the highest and
-// produce the output digits from the lowest).  Each of the 256 lanes of a
-// channel chunk holds 16 bin pairs in registers.  The two radix-4 stages take
-// their input bits from lane bits 4 and 5: v_permlane16_swap and
-// v_permlane32_swap transpose a register bit with lane bit 4 or 5 (a 2x2
-// transpose of a register pair across 16- or 32-lane halves, one instruction
-// per pair of values), so only the exchange before the second radix-16 stage
-// goes through LDS, and detection and downsampling run in registers.  Input
-// bits n0..n11, output bits m0..m11; register bits q0..q3, lane bits L0..L7
-// (L6, L7: the wave):
-//   load     regs n8..n11 (the bin's high digit), lanes L0-3 n0-n3, L4-5
-//            n6-n7, L6-7 n4-n5
-//   A        radix 16 over n8..n11 -> regs m0..m3
-//   permlane regs (m2, m3) <-> lanes (n6, n7)
-//   B        twiddle exp(2 pi i n67 m0..3 / 64), radix 4 over n6, n7 -> regs
-//            (m0, m1, m4, m5); lanes L4-5 = m2, m3
-//   LDS      regs <- n2..n5; lanes L0-3 = m0-m3, L4-5 = n0, n1, L6-7 = m4, m5
-//   C        twiddle exp(2 pi i n0..5 m0..5 / 4096), radix 16 over n2..n5 ->
-//            regs m6..m9
-//   permlane regs (m8, m9) <-> lanes (n0, n1)
-//   D        twiddle exp(2 pi i n01 m6..9 / 64) (the values of B), radix 4
-//            over n0, n1 -> regs (m6, m7, m10, m11); lanes L4-5 = m8, m9
-// Detection adds the two polarisations' power in registers; downsampling by
-// ndec = 2^K sums over m0..m(K-1), lane bits, across lanes (DPP).
+// The 4096-point backward transform y[k] = sum_i x[i] exp(+2 pi i i k / 4096)
+// with i = G0 + 16 G1 + 256 G2 and k = K0 + 16 K1 + 256 K2 (hexadecimal
+// digits) factors as
+//   y = sum_G0 w16^(G0 K2) w4096^(G0 (K0 + 16 K1))
+//         sum_G1 w16^(G1 K1) w256^(G1 K0) sum_G2 w16^(G2 K0) x,
+// i.e. a 16-point DFT over G2, the twiddle w256^(G1 K0), a 16-point DFT over
+// G1, the twiddle w4096^(G0 (K0 + 16 K1)) and a 16-point DFT over G0.  Each
+// of the 256 lanes of a channel chunk holds 16 bin pairs (both polarisations)
+// in registers; lane L = l03 + 16 l45 + 64 w (w the wave).
+//   load        registers G2, lane digits G1 = l03, G0 = l45 + 4 w
+//   pass 1      DFT over G2 -> registers K0; twiddle w256^(G1 K0)
+//   exchange 1  registers K0 <-> lane digit l03 (within each wave)
+//   pass 2      DFT over G1 -> registers K1
+//   exchange 2  registers K1 <-> lane digits (l45, w) (across the waves)
+//   pass 3      twiddle w4096^(G0 L), DFT over G0 -> registers K2
+// so register q of lane L ends with output sample m = L + 256 q.  Detection
+// adds the two polarisations' power in registers; downsampling by ndec = 2^K
+// sums over m's lowest K bits, lane bits, across lanes (DPP).
+//
+// LDS: each wave owns a region of 4 blocks (one per l45) of 16 rows of 17
+// slots (one slot = one bin pair; the padding column keeps the column reads
+// of 16 consecutive lanes on 16 distinct 16-byte bank groups).  Exchange 1
+// writes element (G1, K0) of block (w, l45) at row K0, column G1 and reads it
+// back within the wave; exchange 2 writes element (G0, K0, K1) into the same
+// region (block G0 & 3 of wave G0 >> 2, row K1, column K0), which no other
+// wave touched since the previous barrier, so each DM needs two barriers: one
+// before exchange 1's writes (every wave has read the previous DM's exchange
+// 2) and one between exchange 2's writes and reads.
 
-// exp(+2 pi i (q/4) ((q%4) + 4 l45) / 64) for lane bits (L4, L5) = l45, the
-// twiddles of stages B and D, [l45][q]; and exp(+2 pi i (l45 + 4 q) m / 4096)
-// for the six low output bits m, those of stage C, [m][l45][q].  Filled once
-// per device from double precision.
-__device__ __align__(16) float2 g_twB[4 * 16];
-__device__ __align__(16) float2 g_twC[64 * 4 * 16];
+// exp(+2 pi i g k / 256) at [g][k] (pass 2's twiddles, g = G1, k = K0) and
+// exp(+2 pi i r l / 4096) at [l][r] (pass 3's, r = G0, l = K0 + 16 K1, the
+// lane index).  Filled once per device from double precision.
+__device__ __align__(16) float2 g_tw1[16 * 16];
+__device__ __align__(16) float2 g_tw2[256 * 16];
 
-// 2x2 transposes of (register pair, lane bit 4 / 5) for all four components
-__device__ __forceinline__ void perm16(cpair &a, cpair &b) {
-    const auto x = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
-    const auto y = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
-    const auto z = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.z), __float_as_uint(b.z), false, false);
-    const auto w = __builtin_amdgcn_permlane16_swap(__float_as_uint(a.w), __float_as_uint(b.w), false, false);
-    a = make_float4(__uint_as_float(x[0]), __uint_as_float(y[0]), __uint_as_float(z[0]), __uint_as_float(w[0]));
-    b = make_float4(__uint_as_float(x[1]), __uint_as_float(y[1]), __uint_as_float(z[1]), __uint_as_float(w[1]));
-}
-__device__ __forceinline__ void perm32(cpair &a, cpair &b) {
-    const auto x = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.x), __float_as_uint(b.x), false, false);
-    const auto y = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.y), __float_as_uint(b.y), false, false);
-    const auto z = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.z), __float_as_uint(b.z), false, false);
-    const auto w = __builtin_amdgcn_permlane32_swap(__float_as_uint(a.w), __float_as_uint(b.w), false, false);
-    a = make_float4(__uint_as_float(x[0]), __uint_as_float(y[0]), __uint_as_float(z[0]), __uint_as_float(w[0]));
-    b = make_float4(__uint_as_float(x[1]), __uint_as_float(y[1]), __uint_as_float(z[1]), __uint_as_float(w[1]));
-}
-
-// register bits (q2, q3) <-> lane bits (L4, L5)
-__device__ __forceinline__ void swap_bits_q23_l45(cpair (&v)[16]) {
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        if ((q & 4) == 0)
-            perm16(v[q], v[q + 4]);
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-        perm32(v[q], v[q + 8]);
-}
-
-// twiddle then radix 4 over register bits (q2, q3), for each (q0, q1)
-__device__ __forceinline__ void radix4_q23(cpair (&v)[16], const float2 (&tw)[16]) {
-#pragma unroll
-    for (int q = 4; q < 16; ++q)
-        v[q] = cdmt::pmul(v[q], tw[q]);
-#pragma unroll
-    for (int c = 0; c < 4; ++c)
-        cdmt::dft4<+1>(v[c], v[c + 4], v[c + 8], v[c + 12]);
-}
+constexpr int kX3Region = 4 * 16 * 17;       // bin pairs of LDS per wave
+constexpr int kX3Lds = 4 * kX3Region;        // per workgroup (68 KiB)
 
 // x from lane (lane xor the DPP pattern): quad_perm [1,0,3,2] = lane ^ 1,
 // [2,3,0,1] = lane ^ 2, row_half_mirror = lane ^ 7 within 8 lanes
@@ -546,8 +512,16 @@ __device__ __forceinline__ void fold(const float (&p)[2 * N], float (&r)[N], boo
     }
 }
 
+// Order this wave's LDS accesses before and after (the hardware executes a
+// wave's LDS instructions in order; this keeps the compiler from moving them
+// across).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
-// (K <= 3) and n_d / 2 a multiple of ndec.
+// (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
 template <bool RECUR, int K, class DMS>
 __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
     constexpr int M = 4096;
@@ -557,10 +531,11 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
     const int bs = chunk / a.nchan;
     const int s = bs % a.nsub;
     const int b = bs / a.nsub;
-    const int l45 = (L >> 4) & 3;
+    const int w = L >> 6, l45 = (L >> 4) & 3, l03 = L & 15;
 
-    // bins base + 256 q of this channel, both pols, increasing frequency
-    const int base = (L & 15) + 16 * (L >> 6) + 64 * l45;
+    // bins G0 + 16 G1 + 256 q (G0 = l45 + 4 w, G1 = l03), both pols,
+    // increasing frequency; the transform input index is bin ^ 2048
+    const int base = l45 + 4 * w + 16 * l03;
     cpair raw[16];
     const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M + base;
 #pragma unroll
@@ -585,38 +560,29 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
         g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
-    // twiddles of stages B and D (DM-invariant)
-    float2 twb[16];
+    // pass 3's twiddles (DM-invariant): row L
+    float2 tw2[16];
     {
-        const float4 *row = reinterpret_cast<const float4 *>(g_twB + 16 * l45);
+        const float4 *row = reinterpret_cast<const float4 *>(g_tw2 + 16 * L);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             const float4 x = row[h];
-            twb[2 * h] = make_float2(x.x, x.y);
-            twb[2 * h + 1] = make_float2(x.z, x.w);
+            tw2[2 * h] = make_float2(x.x, x.y);
+            tw2[2 * h + 1] = make_float2(x.z, x.w);
         }
     }
-    const float4 *rowc = reinterpret_cast<const float4 *>(
-        g_twC + 16 * (4 * ((L & 15) + 16 * (L >> 6)) + l45));
+    const float4 *row1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
 
-    // LDS addresses of the exchange (in pairs), XOR-swizzled so that both the
-    // stores and the loads of 16 consecutive lanes hit 16 distinct 16-byte
-    // bank groups: element (regs after = n2..n5, lane after) at
-    // 256 q_after + (lane_after ^ ((n0 + 2 n1) + 4 (n2 + 2 n3)) on 4 bits)
-    int wa[4], ra[4];
-    {
-        const int wbase = 256 * (((L >> 2) & 3) + 4 * (L >> 6)) + 16 * (L & 3) +
-                          4 * (l45 ^ ((L >> 2) & 3));
-        const int rbase = (L & 0xf0) + ((L & 3) ^ l45);
-#pragma unroll
-        for (int c4 = 0; c4 < 4; ++c4) {
-            wa[c4] = wbase + (c4 ^ (L & 3));
-            ra[c4] = rbase + 4 * (((L >> 2) & 3) ^ c4);
-        }
-    }
+    // LDS: writes of both exchanges at xw + 17 k (row k, column l03 of block
+    // (w, l45)); exchange 1 reads at x1r + r (row l03, column r); exchange 2
+    // reads at x2r + kX3Region (r >> 2) + 272 (r & 3) (block G0 = r, row L >> 4,
+    // column l03)
+    cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
+    const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
+    const cpair *const x2r = sh + 17 * (L >> 4) + l03;
 
-    // output: this lane's samples after the sum over the lane bits of
-    // m0..m(K-1); column of the channel in decreasing frequency
+    // output: this lane's samples after the sum over lane bits 0..K-1; column
+    // of the channel in decreasing frequency
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
     const int d0 = dt * a.dm_tile;
     const int d1 = min(a.ndm, d0 + a.dm_tile);
@@ -653,39 +619,46 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
                 v[q ^ 8] = cdmt::pmul(raw[q], make_float2(cs, sn));
             }
         }
-        // A
-        cdmt::dft16<+1>(v);
-        // B
-        swap_bits_q23_l45(v);
-        radix4_q23(v, twb);
-        // stage C's twiddles, fetched across the exchange
-        float2 twc[16];
+        // pass 2's twiddles (row G1), fetched while pass 1 runs
+        float2 tw1[16];
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
-            const float4 x = rowc[h];
-            twc[2 * h] = make_float2(x.x, x.y);
-            twc[2 * h + 1] = make_float2(x.z, x.w);
+            const float4 x = row1[h];
+            tw1[2 * h] = make_float2(x.x, x.y);
+            tw1[2 * h + 1] = make_float2(x.z, x.w);
         }
-        // LDS exchange: the previous DM's loads are done before any store
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            sh[wa[q & 3] + 64 * (q >> 2)] = v[q];
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            v[q] = sh[ra[q & 3] + 256 * q];
-        // C
-#pragma unroll
-        for (int q = 0; q < 16; ++q)
-            v[q] = cdmt::pmul(v[q], twc[q]);
+        // pass 1
         cdmt::dft16<+1>(v);
-        // D
-        swap_bits_q23_l45(v);
-        radix4_q23(v, twb);
+#pragma unroll
+        for (int k = 1; k < 16; ++k)
+            v[k] = cdmt::pmul(v[k], tw1[k]);
+        // exchange 1 (within the wave)
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            xw[17 * k] = v[k];
+        wave_lds_fence();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = x1r[r];
+        // pass 2
+        cdmt::dft16<+1>(v);
+        // exchange 2 (across the waves), into this wave's region
+        wave_lds_fence();
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            xw[17 * k] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = x2r[kX3Region * (r >> 2) + 272 * (r & 3)];
+        // pass 3
+#pragma unroll
+        for (int r = 1; r < 16; ++r)
+            v[r] = cdmt::pmul(v[r], tw2[r]);
+        cdmt::dft16<+1>(v);
 
-        // detection: registers (m6, m7, m10, m11); lanes L0-3 m0-m3, L4-5
-        // m8, m9, L6-7 m4, m5
+        // detection: register q holds sample L + 256 q
         float p[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -693,7 +666,8 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
             p[q] = y.x * y.x + y.y * y.y + y.z * y.z + y.w * y.w;
         }
         const bool b0 = L & 1, b1 = (L >> 1) & 1, b2 = (L >> 2) & 1;
-        // sum over m0..m(K-1): remaining value r is register q(r) with
+        // sum over the lane bits 0..K-1: remaining value r is the sum of
+        // register q(r) over the 2^K lanes L & ~(2^K - 1) + x
         //   K = 0: q = r; K = 1: q = 2 r + L0; K = 2: q = 4 r + 2 L1 + L0;
         //   K = 3: q = 8 r + 4 L1 + 2 L0 + L2
         constexpr int NR = 16 >> K;
@@ -714,12 +688,9 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
             fold<kDppX1, 4>(p1, p2, b0);
             fold<kDppX2, 2>(p2, o, b1);
         }
-        // sample index m of the first summed sample of value r, then the
-        // filterbank sample (m - n_d / 2) / ndec if it is kept
-        const int mlane = (K <= 0 ? (L & 1) : 0) + (K <= 1 ? 2 * ((L >> 1) & 1) : 0) +
-                          (K <= 2 ? 4 * ((L >> 2) & 1) : 0) + 8 * ((L >> 3) & 1) +
-                          16 * ((L >> 6) & 1) + 32 * (L >> 7) + 256 * ((L >> 4) & 1) +
-                          512 * ((L >> 5) & 1);
+        // first summed sample m of value r, then the filterbank sample
+        // (m - n_d / 2) / ndec if it is kept
+        const int mlane = L & ~((1 << K) - 1);
         float *out = a.out + (long long)d * a.ntime_out * a.nch_out +
                      (long long)b * a.tblk * a.t_stride + col * a.col_stride;
 #pragma unroll
@@ -729,8 +700,7 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
             else if constexpr (K == 1) q = 2 * r + (L & 1);
             else if constexpr (K == 2) q = 4 * r + 2 * ((L >> 1) & 1) + (L & 1);
             else q = 8 * r + 4 * ((L >> 1) & 1) + 2 * (L & 1) + ((L >> 2) & 1);
-            const int m = mlane + 64 * (q & 1) + 128 * ((q >> 1) & 1) + 1024 * ((q >> 2) & 1) +
-                          2048 * (q >> 3);
+            const int m = mlane + 256 * q;
             const int tq = (m - a.nd_half) >> K;
             if (m >= a.nd_half && tq < a.tblk)
                 out[(long long)tq * a.t_stride] = o[r];
@@ -740,7 +710,7 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
 
 template <bool RECUR, int K>
 __global__ __launch_bounds__(256, 2) void fused_dedisperse_p(FusedArgs a, DmList dl) {
-    __shared__ cpair sh[4096];
+    __shared__ cpair sh[kX3Lds];
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
     const int ci = lw % a.inner;
     const int rest = lw / a.inner;
@@ -1460,7 +1430,7 @@ struct BatchBeam {
 };
 
 constexpr int kBatchQueues = 8;
-// launch groups: 7 M_bin x 2 transfer-function forms, plus the lane-swap
+// launch groups: 7 M_bin x 2 transfer-function forms, plus the three-pass
 // item's 4 downsampling factors x 2 forms at M_bin = 4096
 constexpr int kBatchGroups = 22;
 
@@ -1469,15 +1439,15 @@ __global__ void batch_reset(unsigned long long *ctr, int n) {
         ctr[i] = 0;
 }
 
-// K >= 0: the M_bin = 4096 lane-swap item (dm_item_p) with ndec = 2^K
+// K >= 0: the M_bin = 4096 three-pass item (dm_item_p) with ndec = 2^K
 template <int M, bool RECUR, int K = -1>
 __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__ beams, int nbeam,
                                                    long long total,
                                                    unsigned long long *__restrict__ ctr) {
     using Sh = FusedShape<M, 16>;
     static_assert(Sh::WG == 256, "batched launches use 256-lane workgroups");
-    static_assert(K < 0 || M == 4096, "the lane-swap item is built for M_bin = 4096");
-    __shared__ cpair sh[K >= 0 ? 4096 : Sh::C * Sh::STRIDE];
+    static_assert(K < 0 || M == 4096, "the three-pass item is built for M_bin = 4096");
+    __shared__ cpair sh[K >= 0 ? kX3Lds : Sh::C * Sh::STRIDE];
     __shared__ long long s_item;
     const int q = blockIdx.x % kBatchQueues;
     const long long lo = total * q / kBatchQueues;
@@ -1571,25 +1541,22 @@ int ensure_twiddles() {
     if (hipMemcpyToSymbol(HIP_SYMBOL(cdmt::g_stage_tw), st.data(),
                           sizeof(float2) * st.size()) != hipSuccess)
         return CDMT_E_DEVICE;
-    // the M_bin = 4096 lane-swap schedule: stages B and D [l45][q], stage C
-    // [m][l45][q]
-    std::vector<float2> tb(4 * 16), tc(64 * 4 * 16);
-    for (int l45 = 0; l45 < 4; ++l45)
-        for (int q = 0; q < 16; ++q) {
-            const long long e = (long long)(q >> 2) * ((q & 3) + 4 * l45);
-            const double ang = 2.0 * M_PI * ((double)(e % 64) / 64.0);
-            tb[16 * l45 + q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    // the M_bin = 4096 three-pass schedule: pass 2 [g][k] = exp(+2 pi i g k / 256),
+    // pass 3 [l][r] = exp(+2 pi i r l / 4096)
+    std::vector<float2> t1(16 * 16), t2(256 * 16);
+    for (int g = 0; g < 16; ++g)
+        for (int k = 0; k < 16; ++k) {
+            const double ang = 2.0 * M_PI * ((double)((g * k) % 256) / 256.0);
+            t1[16 * g + k] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
-    for (int mm = 0; mm < 64; ++mm)
-        for (int l45 = 0; l45 < 4; ++l45)
-            for (int q = 0; q < 16; ++q) {
-                const long long e = (long long)(l45 + 4 * q) * mm;
-                const double ang = 2.0 * M_PI * ((double)(e % 4096) / 4096.0);
-                tc[16 * (4 * mm + l45) + q] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-            }
-    if (hipMemcpyToSymbol(HIP_SYMBOL(g_twB), tb.data(), sizeof(float2) * tb.size()) !=
+    for (int l = 0; l < 256; ++l)
+        for (int r = 0; r < 16; ++r) {
+            const double ang = 2.0 * M_PI * ((double)((l * r) % 4096) / 4096.0);
+            t2[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_tw1), t1.data(), sizeof(float2) * t1.size()) !=
             hipSuccess ||
-        hipMemcpyToSymbol(HIP_SYMBOL(g_twC), tc.data(), sizeof(float2) * tc.size()) !=
+        hipMemcpyToSymbol(HIP_SYMBOL(g_tw2), t2.data(), sizeof(float2) * t2.size()) !=
             hipSuccess)
         return CDMT_E_DEVICE;
     g_init_done[dev] = 1;
@@ -1666,11 +1633,11 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
 
 
 
-// The M_bin = 4096 lane-swap schedule sums ndec = 2^K samples across lanes
+// The M_bin = 4096 three-pass schedule sums ndec = 2^K samples across lanes
 // aligned to multiples of ndec: K for this launch, or -1 when the plan needs
 // the general kernel (other ndec, n_d / 2 not a multiple of ndec, or the
 // schedule switched off).
-int lane_swap_k(const FusedArgs &a) {
+int x3_k(const FusedArgs &a) {
     if (a.schedule != 0)
         return -1;
     for (int k = 0; k <= 3; ++k)
@@ -1732,8 +1699,8 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
                     fused_dedisperse_mx<true, BF><<<grid, WG, 0, st>>>(a, dl);
                 else
                     fused_dedisperse_mx<false, BF><<<grid, WG, 0, st>>>(a, dl);
-            } else if (M == 4096 && R == 16 && lane_swap_k(a) >= 0) {
-                launch_p(recur, lane_swap_k(a), grid, a, dl, st);
+            } else if (M == 4096 && R == 16 && x3_k(a) >= 0) {
+                launch_p(recur, x3_k(a), grid, a, dl, st);
             } else {
                 if (recur)
                     fused_dedisperse<M, R, true><<<grid, WG, 0, st>>>(a, dl);
@@ -2044,7 +2011,7 @@ struct cdmt_batch_s {
     int wg_per_cu = 2;
     long long total = 0;                      // work items over all launches
     struct Launch {
-        int m, recur, k, first, count;        // M_bin, form, lane-swap K (-1: none),
+        int m, recur, k, first, count;        // M_bin, form, three-pass K (-1: none),
         long long items;                      // table rows [first, first + count)
     };
     std::vector<Launch> launches;             // one persistent launch per (M_bin, form)
@@ -2125,7 +2092,7 @@ int batch_upload(cdmt_batch_s *bt) {
                            arithmetic(d.data(), B.ndm, T.a.dm_step);
         T.a.dm_step = recur ? d[1] - d[0] : 0.0;
         rec[b] = recur ? 1 : 0;
-        kk[b] = p->m == 4096 ? lane_swap_k(T.a) : -1;
+        kk[b] = p->m == 4096 ? x3_k(T.a) : -1;
         T.dms = reinterpret_cast<const double *>(bt->ws + bt->dm_off) + dm_at[b];
     }
     for (int m = 64; m <= 4096; m *= 2) {
