@@ -38,6 +38,24 @@ __device__ __forceinline__ cpair pmul(cpair a, float2 w) {
 __device__ __forceinline__ cpair pscale(cpair a, float s) {
     return make_float4(a.x * s, a.y * s, a.z * s, a.w * s);
 }
+// the same operations on a single complex value (one polarisation)
+__device__ __forceinline__ float2 padd(float2 a, float2 b) {
+    return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 psub(float2 a, float2 b) {
+    return make_float2(a.x - b.x, a.y - b.y);
+}
+__device__ __forceinline__ float2 pmul(float2 a, float2 w) {
+    return make_float2(a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x);
+}
+template <int S>
+__device__ __forceinline__ float2 pmuli(float2 a) {
+    if constexpr (S > 0)
+        return make_float2(-a.y, a.x);
+    else
+        return make_float2(a.y, -a.x);
+}
+
 // both complex values times S*i (S = +1 or -1)
 template <int S>
 __device__ __forceinline__ cpair pmuli(cpair a) {
@@ -92,35 +110,61 @@ __device__ __forceinline__ cpair pmul16(cpair a) {
     }
 }
 
+template <int S, int E>
+__device__ __forceinline__ float2 pmul16(float2 a) {
+    constexpr int e = E & 15;
+    if constexpr (e == 0) {
+        return a;
+    } else if constexpr (e == 4) {
+        return pmuli<S>(a);
+    } else if constexpr (e == 8) {
+        return make_float2(-a.x, -a.y);
+    } else if constexpr (e == 12) {
+        return pmuli<-S>(a);
+    } else if constexpr ((e & 3) == 2) {
+        constexpr float h = 0.70710678118654752f;
+        constexpr float cr = (e == 2 || e == 14) ? h : -h;
+        constexpr float ci = (e == 2 || e == 6) ? (S > 0 ? h : -h) : (S > 0 ? -h : h);
+        if constexpr (cr == ci)
+            return make_float2(cr * (a.x - a.y), cr * (a.x + a.y));
+        else
+            return make_float2(cr * (a.x + a.y), cr * (a.y - a.x));
+    } else {
+        constexpr float cr = c16(e);
+        constexpr float ci = S > 0 ? s16(e) : -s16(e);
+        return make_float2(a.x * cr - a.y * ci, a.x * ci + a.y * cr);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Small DFTs in registers: y[k] = sum_n a[n] exp(S 2 pi i n k / r), natural
 // order in and out.
 
-template <int S>
-__device__ __forceinline__ void dft2(cpair *a) {
-    cpair t = a[0];
+template <int S, class T>
+__device__ __forceinline__ void dft2(T *a) {
+    T t = a[0];
     a[0] = padd(t, a[1]);
     a[1] = psub(t, a[1]);
 }
 
-template <int S>
-__device__ __forceinline__ void dft4(cpair &a0, cpair &a1, cpair &a2, cpair &a3) {
-    cpair s02 = padd(a0, a2), d02 = psub(a0, a2);
-    cpair s13 = padd(a1, a3), d13 = pmuli<S>(psub(a1, a3));
+template <int S, class T>
+__device__ __forceinline__ void dft4(T &a0, T &a1, T &a2, T &a3) {
+    T s02 = padd(a0, a2), d02 = psub(a0, a2);
+    T s13 = padd(a1, a3), d13 = pmuli<S>(psub(a1, a3));
     a0 = padd(s02, s13);
     a2 = psub(s02, s13);
     a1 = padd(d02, d13);
     a3 = psub(d02, d13);
 }
 
-template <int S>
-__device__ __forceinline__ void dft4(cpair *a) { dft4<S>(a[0], a[1], a[2], a[3]); }
+template <int S, class T>
+__device__ __forceinline__ void dft4(T *a) { dft4<S>(a[0], a[1], a[2], a[3]); }
 
-template <int S>
-__device__ __forceinline__ void dft8(cpair *a) {
+template <int S, class T>
+__device__ __forceinline__ void dft8(T *a) {
     // even / odd split: y[k] = E[k] + w8^k O[k], y[k+4] = E[k] - w8^k O[k]
-    cpair e[4] = {a[0], a[2], a[4], a[6]};
-    cpair o[4] = {a[1], a[3], a[5], a[7]};
+    T e[4] = {a[0], a[2], a[4], a[6]};
+    T o[4] = {a[1], a[3], a[5], a[7]};
     dft4<S>(e);
     dft4<S>(o);
     o[1] = pmul16<S, 2>(o[1]);
@@ -133,8 +177,8 @@ __device__ __forceinline__ void dft8(cpair *a) {
     }
 }
 
-template <int S>
-__device__ __forceinline__ void dft16(cpair *a) {
+template <int S, class T>
+__device__ __forceinline__ void dft16(T *a) {
     // n = 4m + e: four DFT-4 over m, twiddle w16^(e k'), four DFT-4 over e.
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -152,7 +196,7 @@ __device__ __forceinline__ void dft16(cpair *a) {
     for (int k = 0; k < 4; ++k)
         dft4<S>(a[4 * k], a[4 * k + 1], a[4 * k + 2], a[4 * k + 3]);
     // y[k] sits at a[4 (k mod 4) + k / 4]: transpose the 4x4 block
-    cpair y[16];
+    T y[16];
 #pragma unroll
     for (int k = 0; k < 16; ++k)
         y[k] = a[4 * (k & 3) + (k >> 2)];
@@ -161,8 +205,8 @@ __device__ __forceinline__ void dft16(cpair *a) {
         a[k] = y[k];
 }
 
-template <int R, int S>
-__device__ __forceinline__ void dft(cpair *a) {
+template <int R, int S, class T>
+__device__ __forceinline__ void dft(T *a) {
     if constexpr (R == 16)
         dft16<S>(a);
     else if constexpr (R == 8)

@@ -205,7 +205,7 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
         p->dm_check = value;
         return CDMT_OK;
     case CDMT_OPT_FFT_SCHEDULE:
-        if (value != 0 && value != 1)
+        if (value < 0 || value > 2)
             return CDMT_E_ARG;
         p->fft_schedule = value;
         return CDMT_OK;
