@@ -487,8 +487,6 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
 // lane index).  Filled once per device from double precision.
 __device__ __align__(16) float2 g_tw1[16 * 16];
 __device__ __align__(16) float2 g_tw2[256 * 16];
-// exp(+2 pi i l r / 4096) at [l][r], l, r < 16
-__device__ __align__(16) float2 g_tw4096[16 * 16];
 
 constexpr int kX3Region = 4 * 16 * 17;       // bin pairs of LDS per wave
 constexpr int kX3Lds = 4 * kX3Region;        // per workgroup (68 KiB)
@@ -733,216 +731,6 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_p(FusedArgs a, DmList
     const int dt = rest % a.ndt;
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
     dm_item_p<RECUR, K>(a, ArgDms{dl}, dt, cg, sh);
-}
-
-// The same three passes with the two polarisations transformed one after
-// the other (one complex value per register), so that a lane holds 16
-// complex values of the transform instead of 16 pairs: with the pass-3
-// twiddles formed from two 16 x 16 LDS tables instead of held, a lane needs
-// at most 168 VGPRs and a workgroup 38.5 KiB of LDS, and three workgroups
-// (three waves per SIMD) fit on a compute unit.  Four barriers per DM.
-//   pass-3 twiddle  w4096^(r L) = w4096^(r (L & 15)) w256^(r (L >> 4))
-// LDS: exchange regions as in dm_item_p, one polarisation (8 bytes per
-// slot); then the tables T256[g][k] = w256^(g k) and T4096[l][r] =
-// w4096^(l r), rows padded to 18 values (16-byte reads of 16 lanes with
-// distinct rows hit distinct bank groups).
-constexpr int kPsRow = 18;
-constexpr int kPsLds = 4 * kX3Region + 2 * 16 * kPsRow;   // float2 slots (38.5 KiB)
-
-template <bool RECUR, int K, class DMS>
-__device__ __forceinline__ void dm_item_s(const FusedArgs &a, DMS dms, int dt, int cg, float2 *sh) {
-    constexpr int M = 4096;
-    const int L = threadIdx.x;
-    const int chunk = cg;
-    const int c = chunk % a.nchan;
-    const int bs = chunk / a.nchan;
-    const int s = bs % a.nsub;
-    const int b = bs / a.nsub;
-    const int w = L >> 6, l45 = (L >> 4) & 3, l03 = L & 15;
-
-    float2 *const t256 = sh + 4 * kX3Region;
-    float2 *const t4096 = t256 + 16 * kPsRow;
-    {
-        // 256 lanes fill 2 x 16 rows x 8 float4 (from the device tables)
-        const int tab = L >> 7, row = (L >> 3) & 15, h = L & 7;
-        const float4 *g = reinterpret_cast<const float4 *>(tab ? g_tw4096 : g_tw1);
-        reinterpret_cast<float4 *>(tab ? t4096 : t256)[row * (kPsRow / 2) + h] = g[8 * row + h];
-    }
-
-    const int base = l45 + 4 * w + 16 * l03;
-    cpair raw[16];
-    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M + base;
-#pragma unroll
-    for (int q = 0; q < 16; ++q)
-        raw[q] = src[256 * q];
-
-    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
-    double nu0, off;
-    if (a.chirp_ref == 0) {
-        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
-        off = -0.5 * M;
-    } else {
-        nu0 = fs;
-        off = (double)c * M - 0.5 * a.n;
-    }
-    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
-    double g2[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const double nu = ((double)(base + 256 * q) + off) * a.delta;
-        g2[q] = scale * nu * nu / (nu0 + nu);
-    }
-
-    float2 *const xw = sh + w * kX3Region + 272 * l45 + l03;
-    const float2 *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
-    const float2 *const x2r = sh + 17 * (L >> 4) + l03;
-    const float4 *const ra = reinterpret_cast<const float4 *>(t256 + kPsRow * l03);        // pass 2
-    const float4 *const rb = reinterpret_cast<const float4 *>(t4096 + kPsRow * l03);       // pass 3
-    const float4 *const rc = reinterpret_cast<const float4 *>(t256 + kPsRow * (L >> 4));  // pass 3
-
-    const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
-    const int d0 = dt * a.dm_tile;
-    const int d1 = min(a.ndm, d0 + a.dm_tile);
-
-    float2 step[16];
-    if constexpr (RECUR) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            raw[q] = cdmt::pmul(raw[q], cis_pi_f64(dms[d0] * g2[q]));
-            step[q] = cis_pi_f64(a.dm_step * g2[q]);
-        }
-    }
-    constexpr int NR = 16 >> K;
-    const bool b0 = L & 1, b1 = (L >> 1) & 1, b2 = (L >> 2) & 1;
-
-    for (int d = d0; d < d1; ++d) {
-        float2 h[16];   // transfer function of this DM (exact form only)
-        if constexpr (!RECUR) {
-            const double dm = dms[d];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const double t = dm * g2[q];
-                const double n = rint(t);
-                float sn, cs;
-                sincos_pi(static_cast<float>(t - n), sn, cs);
-                const int flip = static_cast<int>(n) << 31;
-                h[q] = make_float2(__int_as_float(__float_as_int(cs) ^ flip),
-                                   __int_as_float(__float_as_int(sn) ^ flip));
-            }
-        }
-        float o[NR];
-#pragma unroll
-        for (int pol = 0; pol < 2; ++pol) {
-            float2 v[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const float2 x = pol ? make_float2(raw[q].z, raw[q].w) : make_float2(raw[q].x, raw[q].y);
-                // swap halves per channel: bin i -> transform input (i + M/2) mod M
-                if constexpr (RECUR)
-                    v[q ^ 8] = x;
-                else
-                    v[q ^ 8] = cdmt::pmul(x, h[q]);
-            }
-            // pass 1
-            cdmt::dft16<+1>(v);
-            // exchange 1 (within the wave): every wave has read the previous
-            // exchange 2 before the barrier
-            __syncthreads();
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float4 t = ra[k];
-                if (k > 0)
-                    v[2 * k] = cdmt::pmul(v[2 * k], make_float2(t.x, t.y));
-                v[2 * k + 1] = cdmt::pmul(v[2 * k + 1], make_float2(t.z, t.w));
-            }
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                xw[17 * k] = v[k];
-            wave_lds_fence();
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                v[r] = x1r[r];
-            // pass 2
-            cdmt::dft16<+1>(v);
-            // exchange 2 (across the waves), into this wave's region
-            wave_lds_fence();
-#pragma unroll
-            for (int k = 0; k < 16; ++k)
-                xw[17 * k] = v[k];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                v[r] = x2r[kX3Region * (r >> 2) + 272 * (r & 3)];
-            // pass 3
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const float4 tb = rb[k], tc = rc[k];
-                const float2 u0 = cdmt::pmul(make_float2(tb.x, tb.y), make_float2(tc.x, tc.y));
-                const float2 u1 = cdmt::pmul(make_float2(tb.z, tb.w), make_float2(tc.z, tc.w));
-                if (k > 0)
-                    v[2 * k] = cdmt::pmul(v[2 * k], u0);
-                v[2 * k + 1] = cdmt::pmul(v[2 * k + 1], u1);
-            }
-            cdmt::dft16<+1>(v);
-            // this polarisation's power, summed over lane bits 0..K-1 (as in
-            // dm_item_p), added to the other's
-            float p[16];
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                p[q] = v[q].x * v[q].x + v[q].y * v[q].y;
-            float e[NR];
-            if constexpr (K == 0) {
-#pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    e[r] = p[r];
-            } else if constexpr (K == 1) {
-                fold<kDppX1, 8>(p, e, b0);
-            } else if constexpr (K == 2) {
-                float p1[8];
-                fold<kDppX1, 8>(p, p1, b0);
-                fold<kDppX2, 4>(p1, e, b1);
-            } else {
-                float p1[8], p2[4];
-                fold<kDppX7, 8>(p, p1, b2);
-                fold<kDppX1, 4>(p1, p2, b0);
-                fold<kDppX2, 2>(p2, e, b1);
-            }
-#pragma unroll
-            for (int r = 0; r < NR; ++r)
-                o[r] = pol ? o[r] + e[r] : e[r];
-        }
-        if constexpr (RECUR) {
-#pragma unroll
-            for (int q = 0; q < 16; ++q)
-                raw[q] = cdmt::pmul(raw[q], step[q]);
-        }
-        const int mlane = L & ~((1 << K) - 1);
-        float *out = a.out + (long long)d * a.ntime_out * a.nch_out +
-                     (long long)b * a.tblk * a.t_stride + col * a.col_stride;
-#pragma unroll
-        for (int r = 0; r < NR; ++r) {
-            int q;
-            if constexpr (K == 0) q = r;
-            else if constexpr (K == 1) q = 2 * r + (L & 1);
-            else if constexpr (K == 2) q = 4 * r + 2 * ((L >> 1) & 1) + (L & 1);
-            else q = 8 * r + 4 * ((L >> 1) & 1) + 2 * (L & 1) + ((L >> 2) & 1);
-            const int m = mlane + 256 * q;
-            const int tq = (m - a.nd_half) >> K;
-            if (m >= a.nd_half && tq < a.tblk)
-                out[(long long)tq * a.t_stride] = o[r];
-        }
-    }
-}
-
-template <bool RECUR, int K>
-__global__ __launch_bounds__(256, 3) void fused_dedisperse_s(FusedArgs a, DmList dl) {
-    __shared__ float2 sh[kPsLds];
-    const int lw = xcd_remap(blockIdx.x, gridDim.x);
-    const int ci = lw % a.inner;
-    const int rest = lw / a.inner;
-    const int dt = rest % a.ndt;
-    const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
-    dm_item_s<RECUR, K>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1780,15 +1568,6 @@ int ensure_twiddles() {
             const double ang = 2.0 * M_PI * ((double)((l * r) % 4096) / 4096.0);
             t2[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
-    std::vector<float2> t3(16 * 16);
-    for (int l = 0; l < 16; ++l)
-        for (int r = 0; r < 16; ++r) {
-            const double ang = 2.0 * M_PI * ((double)(l * r) / 4096.0);
-            t3[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
-        }
-    if (hipMemcpyToSymbol(HIP_SYMBOL(g_tw4096), t3.data(), sizeof(float2) * t3.size()) !=
-        hipSuccess)
-        return CDMT_E_DEVICE;
     if (hipMemcpyToSymbol(HIP_SYMBOL(g_tw1), t1.data(), sizeof(float2) * t1.size()) !=
             hipSuccess ||
         hipMemcpyToSymbol(HIP_SYMBOL(g_tw2), t2.data(), sizeof(float2) * t2.size()) !=
@@ -1873,7 +1652,7 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
 // the general kernel (other ndec, n_d / 2 not a multiple of ndec, or the
 // schedule switched off).
 int x3_k(const FusedArgs &a) {
-    if (a.schedule != 0 && a.schedule != 2)
+    if (a.schedule != 0)
         return -1;
     for (int k = 0; k <= 3; ++k)
         if (a.ndec == (1 << k))
@@ -1883,19 +1662,6 @@ int x3_k(const FusedArgs &a) {
 
 void launch_p(bool recur, int k, int grid, const FusedArgs &a, const DmList &dl,
               hipStream_t st) {
-    if (a.schedule == 2) {
-        switch (k + (recur ? 4 : 0)) {
-        case 0: fused_dedisperse_s<false, 0><<<grid, 256, 0, st>>>(a, dl); break;
-        case 1: fused_dedisperse_s<false, 1><<<grid, 256, 0, st>>>(a, dl); break;
-        case 2: fused_dedisperse_s<false, 2><<<grid, 256, 0, st>>>(a, dl); break;
-        case 3: fused_dedisperse_s<false, 3><<<grid, 256, 0, st>>>(a, dl); break;
-        case 4: fused_dedisperse_s<true, 0><<<grid, 256, 0, st>>>(a, dl); break;
-        case 5: fused_dedisperse_s<true, 1><<<grid, 256, 0, st>>>(a, dl); break;
-        case 6: fused_dedisperse_s<true, 2><<<grid, 256, 0, st>>>(a, dl); break;
-        default: fused_dedisperse_s<true, 3><<<grid, 256, 0, st>>>(a, dl); break;
-        }
-        return;
-    }
     switch (k + (recur ? 4 : 0)) {
     case 0: fused_dedisperse_p<false, 0><<<grid, 256, 0, st>>>(a, dl); break;
     case 1: fused_dedisperse_p<false, 1><<<grid, 256, 0, st>>>(a, dl); break;
