@@ -72,6 +72,20 @@ def mx_mfma_flops_per_chunk_dm() -> float:
     return 3 * 16 * 6 * (2 * 32 * 32 * 16)
 
 
+def dm_stage_kernel(w, recurrence: bool) -> str:
+    """Name of the FP32 DM-stage kernel the library launches for workload w
+    (default schedule, 16 bins per lane): the three-pass kernel at M_bin =
+    4096 when ndec = 2^K (K <= 3) divides n_d / 2, else the radix-16
+    Stockham kernel."""
+    import math
+    nd_half = w.noverlap // w.nchan // 2
+    k = int(math.log2(w.ndec)) if w.ndec & (w.ndec - 1) == 0 else -1
+    r = "true" if recurrence else "false"
+    if w.m == 4096 and 0 <= k <= 3 and nd_half % w.ndec == 0:
+        return f"fused_dedisperse_x3<{r}, {k}>"
+    return f"fused_dedisperse<{w.m}, 16, {r}>"
+
+
 def fused_flops_per_bin(m: int) -> float:
     """Nominal flops per spectral bin per DM of the fused kernel: for both
     polarisations, complex multiply (6), backward FFT (5 log2 M per point),
@@ -588,6 +602,7 @@ def main():
     fused_bytes = spec_bytes * ntiles + out.numel() * 4
     fwd_bytes = x.numel() * x.element_size() + 3 * spec_bytes
     achieved = flops / fus_avg / 1e12
+    dm_kernel = dm_stage_kernel(w, recurrence=True)
     line = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -608,10 +623,10 @@ def main():
                    "chirp_ref": args.chirp_ref, "dm_tile": dm_tile, "lane_bins": lane_bins,
                    "precision": args.precision,
                    "parallelism": "none"},
-        "roofline": {"kernel": "fused_dedisperse", "bound": "alu",
+        "roofline": {"kernel": dm_kernel, "bound": "alu",
                      "achieved": round(achieved, 3), "peak": round(VALU_FP32_PEAK_TFLOPS, 1),
                      "unit": "TFLOP/s", "frac": round(achieved / VALU_FP32_PEAK_TFLOPS, 4),
-                     "traffic": measured_traffic("fused_dedisperse<%d>" % w.m),
+                     "traffic": measured_traffic(dm_kernel),
                      "hbm_algorithmic_GBs": round(fused_bytes / fus_avg / 1e9, 1),
                      "hbm_frac": round(fused_bytes / fus_avg / 1e9 / HBM_PEAK_GBS, 4)},
         "hbm_copy_GBs": round(copy_gbs, 1),

@@ -523,7 +523,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 // One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
 // (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
 template <bool RECUR, int K, class DMS>
-__device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
+__device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
     constexpr int M = 4096;
     const int L = threadIdx.x;
     const int chunk = cg;
@@ -723,14 +723,14 @@ __device__ __forceinline__ void dm_item_p(const FusedArgs &a, DMS dms, int dt, i
 }
 
 template <bool RECUR, int K>
-__global__ __launch_bounds__(256, 2) void fused_dedisperse_p(FusedArgs a, DmList dl) {
+__global__ __launch_bounds__(256, 2) void fused_dedisperse_x3(FusedArgs a, DmList dl) {
     __shared__ cpair sh[kX3Lds];
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
     const int ci = lw % a.inner;
     const int rest = lw / a.inner;
     const int dt = rest % a.ndt;
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
-    dm_item_p<RECUR, K>(a, ArgDms{dl}, dt, cg, sh);
+    dm_item_x3<RECUR, K>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1453,7 +1453,7 @@ __global__ void batch_reset(unsigned long long *ctr, int n) {
         ctr[i] = 0;
 }
 
-// K >= 0: the M_bin = 4096 three-pass item (dm_item_p) with ndec = 2^K
+// K >= 0: the M_bin = 4096 three-pass item (dm_item_x3) with ndec = 2^K
 template <int M, bool RECUR, int K = -1>
 __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__ beams, int nbeam,
                                                    long long total,
@@ -1488,7 +1488,7 @@ __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__
         const int dt = (int)(rest % a.ndt);
         const int cg = (int)((rest / a.ndt) * a.inner + ci);
         if constexpr (K >= 0)
-            dm_item_p<RECUR, K>(a, MemDms{beams[b].dms}, dt, cg, sh);
+            dm_item_x3<RECUR, K>(a, MemDms{beams[b].dms}, dt, cg, sh);
         else
             dm_item<M, 16, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
     }
@@ -1660,17 +1660,17 @@ int x3_k(const FusedArgs &a) {
     return -1;
 }
 
-void launch_p(bool recur, int k, int grid, const FusedArgs &a, const DmList &dl,
+void launch_x3(bool recur, int k, int grid, const FusedArgs &a, const DmList &dl,
               hipStream_t st) {
     switch (k + (recur ? 4 : 0)) {
-    case 0: fused_dedisperse_p<false, 0><<<grid, 256, 0, st>>>(a, dl); break;
-    case 1: fused_dedisperse_p<false, 1><<<grid, 256, 0, st>>>(a, dl); break;
-    case 2: fused_dedisperse_p<false, 2><<<grid, 256, 0, st>>>(a, dl); break;
-    case 3: fused_dedisperse_p<false, 3><<<grid, 256, 0, st>>>(a, dl); break;
-    case 4: fused_dedisperse_p<true, 0><<<grid, 256, 0, st>>>(a, dl); break;
-    case 5: fused_dedisperse_p<true, 1><<<grid, 256, 0, st>>>(a, dl); break;
-    case 6: fused_dedisperse_p<true, 2><<<grid, 256, 0, st>>>(a, dl); break;
-    default: fused_dedisperse_p<true, 3><<<grid, 256, 0, st>>>(a, dl); break;
+    case 0: fused_dedisperse_x3<false, 0><<<grid, 256, 0, st>>>(a, dl); break;
+    case 1: fused_dedisperse_x3<false, 1><<<grid, 256, 0, st>>>(a, dl); break;
+    case 2: fused_dedisperse_x3<false, 2><<<grid, 256, 0, st>>>(a, dl); break;
+    case 3: fused_dedisperse_x3<false, 3><<<grid, 256, 0, st>>>(a, dl); break;
+    case 4: fused_dedisperse_x3<true, 0><<<grid, 256, 0, st>>>(a, dl); break;
+    case 5: fused_dedisperse_x3<true, 1><<<grid, 256, 0, st>>>(a, dl); break;
+    case 6: fused_dedisperse_x3<true, 2><<<grid, 256, 0, st>>>(a, dl); break;
+    default: fused_dedisperse_x3<true, 3><<<grid, 256, 0, st>>>(a, dl); break;
     }
 }
 
@@ -1714,7 +1714,7 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
                 else
                     fused_dedisperse_mx<false, BF><<<grid, WG, 0, st>>>(a, dl);
             } else if (M == 4096 && R == 16 && x3_k(a) >= 0) {
-                launch_p(recur, x3_k(a), grid, a, dl, st);
+                launch_x3(recur, x3_k(a), grid, a, dl, st);
             } else {
                 if (recur)
                     fused_dedisperse<M, R, true><<<grid, WG, 0, st>>>(a, dl);
@@ -2149,7 +2149,7 @@ void batch_launch(int recur, const BatchBeam *tab, int count, long long items,
         dm_batch<M, false><<<grid, 256, 0, st>>>(tab, count, items, ctr);
 }
 
-void batch_launch_p(int recur, int k, const BatchBeam *tab, int count, long long items,
+void batch_launch_x3(int recur, int k, const BatchBeam *tab, int count, long long items,
                     unsigned long long *ctr, int grid, hipStream_t st) {
     switch (k + (recur ? 4 : 0)) {
     case 0: dm_batch<4096, false, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
@@ -2193,7 +2193,7 @@ int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
         unsigned long long *c = ctr + k * kBatchQueues;
         const BatchBeam *t = tab + L.first;
         if (L.k >= 0) {
-            batch_launch_p(L.recur, L.k, t, L.count, L.items, c, grid, st);
+            batch_launch_x3(L.recur, L.k, t, L.count, L.items, c, grid, st);
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
             continue;

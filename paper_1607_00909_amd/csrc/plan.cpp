@@ -167,7 +167,7 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
         p->sign = value;
         return CDMT_OK;
     case CDMT_OPT_PRECISION:
-        if (value != 0 && value != 1)
+        if (value < 0 || value > 2)
             return CDMT_E_ARG;
         if (value != 0 && p->m != 4096)
             return CDMT_E_UNSUPPORTED;
@@ -205,7 +205,7 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
         p->dm_check = value;
         return CDMT_OK;
     case CDMT_OPT_FFT_SCHEDULE:
-        if (value < 0 || value > 2)
+        if (value != 0 && value != 1)
             return CDMT_E_ARG;
         p->fft_schedule = value;
         return CDMT_OK;
