@@ -1291,6 +1291,188 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
         part[(long long)(dm_first + d) * ncg_all + cg] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// The DM gradient at M_bin = 4096 on the three-pass transforms (any ndec).
+// Per DM of the workgroup's tile: the chirped spectrum S' (exact transfer
+// function) is transformed as in dm_item_x3 (register q of lane L ends with
+// sample m = L + 256 q); g_y = 2 G y on the kept samples; then the adjoint
+// transform (e-) takes the passes in reverse digit order,
+//   input m = M0 + 16 M1 + 256 M2 (M0 = L & 15, M1 = L >> 4, M2 = q),
+//   pass 1  DFT over M2 -> registers J0; twiddle w256^-(M1 J0)
+//   exchange A (across the waves, the transpose of exchange 2): registers
+//           <- M1, lane digit L >> 4 <- J0
+//   pass 2  DFT over M1 -> registers J1
+//   exchange B (within the wave, the transpose of exchange 1): registers
+//           <- M0, lane digit L & 15 <- J1
+//   pass 3  twiddle w4096^-(M0 (J0 + 16 J1)), DFT over M0 -> registers J2
+// so register q of lane L holds g_x at index j = (L >> 4) + 16 (L & 15) +
+// 256 q, which is the bin the lane loaded into register q ^ 8 (the swap of
+// halves).  The per-bin terms Re(conj(g_S') i S') g2 are summed in FP64.
+// Exchange B writes into the slots its own wave read in exchange A, so the
+// next DM's exchange 1 needs no barrier: three barriers per DM.
+constexpr int kGradTile = 16;
+
+template <int TILE>
+__global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
+                                                     const float *__restrict__ gout,
+                                                     double *__restrict__ part, long long ncg_all,
+                                                     int dm_first) {
+    constexpr int M = 4096;
+    __shared__ cpair sh[kX3Lds];
+    __shared__ double red[4][TILE];
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int ci = lw % a.inner;
+    const int rest = lw / a.inner;
+    const int dt = rest % a.ndt;
+    const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
+    const int L = threadIdx.x;
+    const int c = cg % a.nchan;
+    const int bs = cg / a.nchan;
+    const int s = bs % a.nsub;
+    const int b = bs / a.nsub;
+    const int w = L >> 6, l45 = (L >> 4) & 3, l03 = L & 15;
+    const int base = l45 + 4 * w + 16 * l03;
+    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M + base;
+
+    const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
+    double nu0, off;
+    if (a.chirp_ref == 0) {
+        nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
+        off = -0.5 * M;
+    } else {
+        nu0 = fs;
+        off = (double)c * M - 0.5 * a.n;
+    }
+    const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
+    double g2[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const double nu = ((double)(base + 256 * q) + off) * a.delta;
+        g2[q] = scale * nu * nu / (nu0 + nu);
+    }
+
+    cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
+    const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
+    cpair *const x2 = sh + 17 * (L >> 4) + l03;
+    const float4 *const r1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
+    const float4 *const r2 = reinterpret_cast<const float4 *>(g_tw2 + 16 * L);
+    const float4 *const r1b = reinterpret_cast<const float4 *>(g_tw1 + 16 * (L >> 4));
+    const float4 *const r2b =
+        reinterpret_cast<const float4 *>(g_tw2 + 16 * ((L >> 4) + 16 * l03));
+    const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
+    const int d0 = dt * a.dm_tile;
+    const int d1 = min(a.ndm, d0 + a.dm_tile);
+    // offset of dL/dF for sample m = L + 256 q within the DM's block column,
+    // or -1 when m is discarded (the n_d / 2 samples at either edge)
+    int goff[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int m = L + 256 * q;
+        goff[q] = (m >= a.nd_half && m < M - a.nd_half) ? (m - a.nd_half) / a.ndec * a.t_stride
+                                                         : -1;
+    }
+
+    // twiddle multiply from a row of 8 float4 (conjugated for the adjoint)
+    auto twiddle = [](cpair (&v)[16], const float4 *row, bool conj) {
+#pragma unroll
+        for (int h = 0; h < 8; ++h) {
+            const float4 x = row[h];
+            const float sy = conj ? -1.f : 1.f;
+            if (h > 0)
+                v[2 * h] = cdmt::pmul(v[2 * h], make_float2(x.x, sy * x.y));
+            v[2 * h + 1] = cdmt::pmul(v[2 * h + 1], make_float2(x.z, sy * x.w));
+        }
+    };
+
+    for (int d = d0; d < d1; ++d) {
+        const double dm = dl.dm[d];
+        float2 h[16];
+        cpair v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const double ph = dm * g2[q];
+            const double n = rint(ph);
+            float sn, cs;
+            sincos_pi(static_cast<float>(ph - n), sn, cs);
+            const int flip = static_cast<int>(n) << 31;
+            h[q] = make_float2(__int_as_float(__float_as_int(cs) ^ flip),
+                               __int_as_float(__float_as_int(sn) ^ flip));
+            v[q ^ 8] = cdmt::pmul(src[256 * q], h[q]);
+        }
+        // y: pass 1, exchange 1 (within the wave), pass 2, exchange 2
+        cdmt::dft16<+1>(v);
+        twiddle(v, r1, false);
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            xw[17 * k] = v[k];
+        wave_lds_fence();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = x1r[r];
+        cdmt::dft16<+1>(v);
+        wave_lds_fence();
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            xw[17 * k] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = x2[kX3Region * (r >> 2) + 272 * (r & 3)];
+        twiddle(v, r2, false);
+        cdmt::dft16<+1>(v);
+        // g_y = 2 G y on the kept samples m = L + 256 q
+        const float *g = gout + (long long)d * a.ntime_out * a.nch_out +
+                         (long long)b * a.tblk * a.t_stride + col * a.col_stride;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const float gi = g[goff[q] < 0 ? 0 : goff[q]];
+            v[q] = cdmt::pscale(v[q], goff[q] < 0 ? 0.f : 2.0f * gi);
+        }
+        // g_x: pass 1 (e-), exchange A (across the waves)
+        cdmt::dft16<-1>(v);
+        twiddle(v, r1b, true);
+        __syncthreads();                   // every wave has read exchange 2
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            x2[kX3Region * (k >> 2) + 272 * (k & 3)] = v[k];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = xw[17 * r];
+        // pass 2, exchange B (within the wave, the slots read in exchange A)
+        cdmt::dft16<-1>(v);
+        wave_lds_fence();
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            xw[17 * k] = v[k];
+        wave_lds_fence();
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+            v[r] = x1r[r];
+        twiddle(v, r2b, true);
+        cdmt::dft16<-1>(v);
+        // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols (the
+        // spectrum is re-read, not held through the transforms)
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const cpair gz = v[q ^ 8];
+            const cpair x = cdmt::pmul(src[256 * q], h[q]);
+            const float tx = gz.y * x.x - gz.x * x.y;
+            const float ty = gz.w * x.z - gz.z * x.w;
+            acc = fma(g2[q], (double)tx + (double)ty, acc);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            acc += __shfl_xor(acc, o);
+        if ((L & 63) == 0)
+            red[w][d - d0] = acc;
+    }
+    __syncthreads();
+    if (L < d1 - d0)
+        part[(long long)(dm_first + d0 + L) * ncg_all + cg] =
+            (red[0][L] + red[1][L]) + (red[2][L] + red[3][L]);
+}
+
 // Gradient with respect to the voltages, one DM: the adjoint continued
 // through the transfer function and the forward stage.  dv_spec forms, per
 // chunk, g_spec = g_S' conj(H) as dm_grad does, and stores conj(g_spec) / N
@@ -1799,6 +1981,21 @@ int launch_grad_m(const FusedArgs &a0, const double *dms, int ndm, const float *
         // groups together), and launches cut at multiples of it
         const int C = 4096 / M;
         a.inner = a0.nchan >= C ? a0.nchan / C : 1;
+        if (M == 4096 && a0.schedule == 0 && (long long)a0.tblk * a0.t_stride < 0x7fffffffLL) {
+            // three-pass kernel, DM tiles of kGradTile
+            a.dm_tile = kGradTile;
+            a.ndt = (cnt + kGradTile - 1) / kGradTile;
+            const long long per = kMaxGroups / a.ndt / a.inner * a.inner;
+            for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
+                const long long n = ncg - cg0 < per ? ncg - cg0 : per;
+                a.cg0 = (int)cg0;
+                dm_grad_x3<kGradTile><<<(unsigned)(n * a.ndt), 256, 0, st>>>(a, dl, g, part, ncg,
+                                                                            first);
+                if (hipGetLastError() != hipSuccess)
+                    return CDMT_E_DEVICE;
+            }
+            continue;
+        }
         const long long per = kMaxGroups / cnt / a.inner * a.inner;
         for (long long cg0 = 0; cg0 < ncg; cg0 += per) {
             const long long n = ncg - cg0 < per ? ncg - cg0 : per;
