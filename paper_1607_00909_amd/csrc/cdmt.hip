@@ -537,26 +537,38 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
     // increasing frequency; the transform input index is bin ^ 2048
     const int base = l45 + 4 * w + 16 * l03;
     cpair raw[16];
-    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M + base;
+    {
+        // the chunk as a raw buffer (uniform descriptor), row q at a scalar
+        // offset of 4096 q bytes from this lane's 32-bit offset
+        const cpair *chunk = a.spec + (long long)bs * a.n + (long long)c * M;
+        const __amdgpu_buffer_rsrc_t view = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<cpair *>(chunk), (short)0, M * 16, 0x00020000);
 #pragma unroll
-    for (int q = 0; q < 16; ++q)
-        raw[q] = src[256 * q];
+        for (int q = 0; q < 16; ++q)
+            raw[q] = __builtin_bit_cast(
+                cpair, __builtin_amdgcn_raw_buffer_load_b128(view, 16 * base, 4096 * q, 0));
+    }
 
     // DM-independent part of Eq. 1 per bin (as in dm_item)
     const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
     double nu0, off;
+    int cofs;   // bin offset of the channel within the frequency axis of nu
     if (a.chirp_ref == 0) {
         nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
         off = -0.5 * M;
+        cofs = 0;
     } else {
         nu0 = fs;
-        off = (double)c * M - 0.5 * a.n;
+        off = -0.5 * a.n;
+        cofs = c * M;
     }
     const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
     double g2[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const double nu = ((double)(base + 256 * q) + off) * a.delta;
+        // (the bin's index converted per item: a per-lane constant held
+        // across a batch's items would cost 32 registers)
+        const double nu = ((double)(base + 256 * q + cofs) + off) * a.delta;
         g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
@@ -1331,22 +1343,31 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
     const int b = bs / a.nsub;
     const int w = L >> 6, l45 = (L >> 4) & 3, l03 = L & 15;
     const int base = l45 + 4 * w + 16 * l03;
-    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M + base;
+    // the chunk as a raw buffer (uniform descriptor) and this lane's byte
+    // offset: the load of row q adds 4096 q bytes as a scalar offset, so no
+    // per-row addresses are held
+    const cpair *chunk = a.spec + (long long)bs * a.n + (long long)c * M;
+    const __amdgpu_buffer_rsrc_t spec_view =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<cpair *>(chunk), (short)0, M * 16, 0x00020000);
+    const int lane_off = 16 * base;
 
     const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
     double nu0, off;
+    int cofs;
     if (a.chirp_ref == 0) {
         nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
         off = -0.5 * M;
+        cofs = 0;
     } else {
         nu0 = fs;
-        off = (double)c * M - 0.5 * a.n;
+        off = -0.5 * a.n;
+        cofs = c * M;
     }
     const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
     double g2[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
-        const double nu = ((double)(base + 256 * q) + off) * a.delta;
+        const double nu = ((double)(base + 256 * q + cofs) + off) * a.delta;
         g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
@@ -1361,14 +1382,15 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
     const int d0 = dt * a.dm_tile;
     const int d1 = min(a.ndm, d0 + a.dm_tile);
-    // offset of dL/dF for sample m = L + 256 q within the DM's block column,
-    // or -1 when m is discarded (the n_d / 2 samples at either edge)
-    int goff[16];
+    // filterbank sample of m = L + 256 q within the block, two 16-bit values
+    // per register (0xffff: m is discarded, the n_d / 2 samples at either edge)
+    unsigned tpk[8];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int m = L + 256 * q;
-        goff[q] = (m >= a.nd_half && m < M - a.nd_half) ? (m - a.nd_half) / a.ndec * a.t_stride
-                                                         : -1;
+    for (int q = 0; q < 16; q += 2) {
+        const int m0 = L + 256 * q, m1 = m0 + 256;
+        const unsigned t0 = (m0 >= a.nd_half && m0 < M - a.nd_half) ? (m0 - a.nd_half) / a.ndec : 0xffffu;
+        const unsigned t1 = (m1 >= a.nd_half && m1 < M - a.nd_half) ? (m1 - a.nd_half) / a.ndec : 0xffffu;
+        tpk[q / 2] = t0 | (t1 << 16);
     }
 
     // twiddle multiply from a row of 8 float4 (conjugated for the adjoint)
@@ -1385,8 +1407,8 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
 
     for (int d = d0; d < d1; ++d) {
         const double dm = dl.dm[d];
-        float2 h[16];
-        cpair v[16];
+        // the chirped spectrum S' of this DM, held for the final product
+        cpair sp[16], v[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const double ph = dm * g2[q];
@@ -1394,9 +1416,12 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
             float sn, cs;
             sincos_pi(static_cast<float>(ph - n), sn, cs);
             const int flip = static_cast<int>(n) << 31;
-            h[q] = make_float2(__int_as_float(__float_as_int(cs) ^ flip),
-                               __int_as_float(__float_as_int(sn) ^ flip));
-            v[q ^ 8] = cdmt::pmul(src[256 * q], h[q]);
+            const float2 h = make_float2(__int_as_float(__float_as_int(cs) ^ flip),
+                                         __int_as_float(__float_as_int(sn) ^ flip));
+            const cpair x = __builtin_bit_cast(
+                cpair, __builtin_amdgcn_raw_buffer_load_b128(spec_view, lane_off, 4096 * q, 0));
+            sp[q] = cdmt::pmul(x, h);
+            v[q ^ 8] = sp[q];
         }
         // y: pass 1, exchange 1 (within the wave), pass 2, exchange 2
         cdmt::dft16<+1>(v);
@@ -1424,8 +1449,10 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
                          (long long)b * a.tblk * a.t_stride + col * a.col_stride;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-            const float gi = g[goff[q] < 0 ? 0 : goff[q]];
-            v[q] = cdmt::pscale(v[q], goff[q] < 0 ? 0.f : 2.0f * gi);
+            const unsigned tq = (q & 1) ? tpk[q / 2] >> 16 : tpk[q / 2] & 0xffffu;
+            const bool kept = tq != 0xffffu;
+            const float gi = g[(kept ? tq : 0u) * a.t_stride];
+            v[q] = cdmt::pscale(v[q], kept ? 2.0f * gi : 0.f);
         }
         // g_x: pass 1 (e-), exchange A (across the waves)
         cdmt::dft16<-1>(v);
@@ -1450,13 +1477,12 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
             v[r] = x1r[r];
         twiddle(v, r2b, true);
         cdmt::dft16<-1>(v);
-        // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols (the
-        // spectrum is re-read, not held through the transforms)
+        // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const cpair gz = v[q ^ 8];
-            const cpair x = cdmt::pmul(src[256 * q], h[q]);
+            const cpair x = sp[q];
             const float tx = gz.y * x.x - gz.x * x.y;
             const float ty = gz.w * x.z - gz.z * x.w;
             acc = fma(g2[q], (double)tx + (double)ty, acc);
