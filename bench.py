@@ -150,9 +150,9 @@ def cpu_baseline(w, x_dev, npairs: int, threads: int, outputs=None, pulses=()):
 def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
     """The batched workload: 24 beams, each with its own subbands, N_bin,
     channels, overlap, DM list and output, in one persistent DM-stage launch
-    per M_bin (all beams here have M_bin = 4096: one launch), replayed as a
-    hipGraph after the autotuner picked each beam's forward-FFT split, the DM
-    tile and the grid."""
+    per M_bin (1024, 2048 and 4096 here), replayed as a hipGraph after the
+    autotuner picked each beam's forward-FFT split, the DM-stage schedule of
+    the M_bin = 4096 beams, the DM tile and the grid."""
     import math
     draws = synth.batch_draws()
     beams, dm_seconds = [], 0.0
@@ -192,6 +192,17 @@ def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
                batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_FWD_N2) !=
                cdmt.cdmt_plan_get(b[0].handle, cdmt.CDMT_OPT_FWD_N2)
                for i, b in enumerate(beams)),
+           "m_bins": {str(m): sum(1 for d in draws if d.nfft // d.nchan == m)
+                      for m in sorted({d.nfft // d.nchan for d in draws})},
+           # the DM-stage radix schedule the autotuner kept per M_bin: "x3"
+           # three radix-16 passes, "s16" / "s8" radix-16 / radix-8 Stockham
+           "dm_stage_radix": {str(m): sorted({
+               "x3" if batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_FFT_SCHEDULE) == 0 and m == 4096
+               and batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_LANE_BINS) == 16
+               else "s%d" % (8 if batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_LANE_BINS) == 8
+                             and m >= 2048 else 16)
+               for i, d in enumerate(draws) if d.nfft // d.nchan == m})
+               for m in sorted({d.nfft // d.nchan for d in draws})},
            "autotune_best_ms": round(tuned_ms, 3), "autotune_s": round(tune_s, 1),
            "graph": True}
     log(f"batch: {len(draws)} beams, {ms:.3f} ms per run, {res['value']} DM-s/s")

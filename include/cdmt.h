@@ -289,8 +289,8 @@ int cdmt_redigitise(const float *filterbank, int ndm, long long ntime, int nchan
  * launch when all share M_bin), whose workgroups take (beam, chunk group, DM
  * tile) items from per-XCD work queues until all are done.  Results are
  * bitwise equal to cdmt_dedisperse of each beam with the same DM tile.
- * Restrictions: FP32 precision, 16 bins per lane, M_bin <= 4096
- * (CDMT_E_UNSUPPORTED otherwise).
+ * Restrictions: FP32 precision, M_bin <= 4096 (CDMT_E_UNSUPPORTED
+ * otherwise).
  */
 typedef struct cdmt_batch_s *cdmt_batch_t;
 
@@ -331,11 +331,22 @@ int cdmt_batch_set(cdmt_batch_t batch, int opt, int value);
 int cdmt_batch_get(cdmt_batch_t batch, int opt, long long *value);
 
 /* Per-beam settings of a batch (enum cdmt_batch_beam_opt), beam = index in
- * the creation order.  CDMT_BATCH_BEAM_FWD_N2: the forward FFT's split for
- * that beam (as CDMT_OPT_FWD_N2; set 0 to use the beam plan's own); the
- * beam's plan is not modified. */
+ * the creation order; the beam's plan is not modified.
+ * CDMT_BATCH_BEAM_FWD_N2: the forward FFT's split for that beam (as
+ * CDMT_OPT_FWD_N2; set 0 to use the beam plan's own).
+ * CDMT_BATCH_BEAM_FFT_SCHEDULE: the DM stage's schedule for that beam (as
+ * CDMT_OPT_FFT_SCHEDULE, 0 or 1; -1 to use the beam plan's own).
+ * CDMT_BATCH_BEAM_LANE_BINS: bins per lane of its DM stage (as
+ * CDMT_OPT_LANE_BINS, 8 or 16, taking effect at M_bin = 2048 and 4096 with
+ * the Stockham stages; 0 to use the beam plan's own).
+ * These two decide the beam's launch group, so setting one rewrites the
+ * item table after a device-wide synchronisation; results are bitwise equal
+ * to cdmt_dedisperse of the beam with the same settings (and the batch's DM
+ * tile). */
 enum cdmt_batch_beam_opt {
-    CDMT_BATCH_BEAM_FWD_N2 = 0
+    CDMT_BATCH_BEAM_FWD_N2 = 0,
+    CDMT_BATCH_BEAM_FFT_SCHEDULE = 1,
+    CDMT_BATCH_BEAM_LANE_BINS = 2
 };
 int cdmt_batch_beam_set(cdmt_batch_t batch, int beam, int opt, int value);
 int cdmt_batch_beam_get(cdmt_batch_t batch, int beam, int opt, int *value);
@@ -352,10 +363,15 @@ int cdmt_batch_run_graph(cdmt_batch_t batch, void *hip_stream);
 /* Autotune the batch on hip_stream.  First the radix schedule of each
  * beam's forward FFT: every valid split N1 x N2 (CDMT_OPT_FWD_N2) of the
  * beam's N_bin is timed on that beam's forward stage alone and the fastest
- * kept (CDMT_BATCH_BEAM_FWD_N2).  Then the whole batch for every DM tile in
- * {4, 8, 16} and 2 or 4 workgroups per CU; the fastest setting is kept and
- * its time per run returned in *best_ms (may be NULL).  reps runs per
- * candidate after one warm-up.  Writes the beams' outputs. */
+ * kept (CDMT_BATCH_BEAM_FWD_N2).  Then the DM stage's radix schedule per
+ * M_bin (beams of one M_bin share launches), each candidate timed on the
+ * whole batch: at M_bin = 4096 the three-pass transform, radix-16 and radix-8
+ * Stockham stages; at 2048 radix 16 and 8 (CDMT_BATCH_BEAM_FFT_SCHEDULE,
+ * CDMT_BATCH_BEAM_LANE_BINS).  Then the
+ * whole batch for every DM tile in {4, 8, 16} and 2 or 4 workgroups per CU;
+ * the fastest setting is kept and its time per run returned in *best_ms
+ * (may be NULL).  reps runs per candidate after one warm-up.  Writes the
+ * beams' outputs. */
 int cdmt_batch_autotune(cdmt_batch_t batch, void *hip_stream, int reps, float *best_ms);
 
 /* Free a batch and its graph (NULL is accepted). */

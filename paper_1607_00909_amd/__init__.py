@@ -45,6 +45,8 @@ EXPORTS = ("cdmt_plan", "cdmt_plan_set", "cdmt_plan_get", "cdmt_noverlap_for", "
 CDMT_BATCH_DM_TILE, CDMT_BATCH_WG_PER_CU, CDMT_BATCH_ITEMS, CDMT_BATCH_LAUNCHES = 0, 1, 2, 3
 # enum cdmt_batch_beam_opt
 CDMT_BATCH_BEAM_FWD_N2 = 0
+CDMT_BATCH_BEAM_FFT_SCHEDULE = 1
+CDMT_BATCH_BEAM_LANE_BINS = 2
 
 
 class Beam(ctypes.Structure):

@@ -333,28 +333,39 @@ __device__ __forceinline__ void dm_item(const FusedArgs &a, DMS dms, int dt, int
 
     // this channel's M bins, both pols, increasing frequency
     cpair raw[R];
-    const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
+    {
+        // the chunk as a raw buffer (no records when this lane's chunk is
+        // past the end: the loads return zeros), row q at a scalar offset
+        const cpair *src = a.spec + (long long)bs * a.n + (long long)c * M;
+        const __amdgpu_buffer_rsrc_t view = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<cpair *>(src), (short)0, valid ? M * 16 : 0, 0x00020000);
 #pragma unroll
-    for (int q = 0; q < R; ++q)
-        raw[q] = valid ? src[tt + T * q] : make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int q = 0; q < R; ++q)
+            raw[q] = __builtin_bit_cast(
+                cpair, __builtin_amdgcn_raw_buffer_load_b128(view, 16 * tt, 16 * T * q, 0));
+    }
 
     // DM-independent part of Eq. 1 per bin: g2 = 2 * sign * 1e6 k_DM nu^2 /
     // (nu0^2 (nu0 + nu)), nu = offset from nu0 in MHz, so that for DM d the
     // transfer function exp(sign 2 pi i DM g) = exp(i pi DM g2).
     const double fs = a.f_centre + ((double)s - 0.5 * (a.nsub - 1)) * a.bw;
     double nu0, off;
+    int cofs;   // bin offset of the channel within the frequency axis of nu
     if (a.chirp_ref == 0) {
         nu0 = fs - 0.5 * a.bw + ((double)c + 0.5) * a.bw / a.nchan;
         off = -0.5 * M;
+        cofs = 0;
     } else {
         nu0 = fs;
-        off = (double)c * M - 0.5 * a.n;
+        off = -0.5 * a.n;
+        cofs = c * M;
     }
     const double scale = 2.0 * a.sign * a.kk / (nu0 * nu0);
     double g2[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-        const double nu = ((double)(tt + T * q) + off) * a.delta;
+        // (the bin's index converted per item, not held across a batch's items)
+        const double nu = ((double)(tt + T * q + cofs) + off) * a.delta;
         g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
@@ -585,13 +596,15 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
     }
     const float4 *row1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
 
-    // LDS: writes of both exchanges at xw + 17 k (row k, column l03 of block
-    // (w, l45)); exchange 1 reads at x1r + r (row l03, column r); exchange 2
-    // reads at x2r + kX3Region (r >> 2) + 272 (r & 3) (block G0 = r, row L >> 4,
-    // column l03)
+    // LDS: exchange 1 writes at xw + 17 k (row k of 17 slots, column l03 of
+    // block (w, l45)) and reads at x1r + r (row l03, column r); exchange 2
+    // writes at xw + 16 k (rows of 16) and reads at x2r + kX3Region (r >> 2) +
+    // 272 (r & 3) (block G0 = r, row L >> 4, column l03).  The block pitch
+    // (272 = 16 mod 64 slots) and the row pitches keep all 64 lanes of a wave
+    // on distinct 16-byte bank groups of 64 banks in every access.
     cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
     const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
-    const cpair *const x2r = sh + 17 * (L >> 4) + l03;
+    const cpair *const x2r = sh + 16 * (L >> 4) + l03;
 
     // output: this lane's samples after the sum over lane bits 0..K-1; column
     // of the channel in decreasing frequency
@@ -662,7 +675,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         wave_lds_fence();
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            xw[17 * k] = v[k];
+            xw[16 * k] = v[k];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r)
@@ -1373,7 +1386,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
 
     cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
     const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
-    cpair *const x2 = sh + 17 * (L >> 4) + l03;
+    cpair *const x2 = sh + 16 * (L >> 4) + l03;
     const float4 *const r1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
     const float4 *const r2 = reinterpret_cast<const float4 *>(g_tw2 + 16 * L);
     const float4 *const r1b = reinterpret_cast<const float4 *>(g_tw1 + 16 * (L >> 4));
@@ -1437,7 +1450,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         wave_lds_fence();
 #pragma unroll
         for (int k = 0; k < 16; ++k)
-            xw[17 * k] = v[k];
+            xw[16 * k] = v[k];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r)
@@ -1464,7 +1477,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            v[r] = xw[17 * r];
+            v[r] = xw[16 * r];
         // pass 2, exchange B (within the wave, the slots read in exchange A)
         cdmt::dft16<-1>(v);
         wave_lds_fence();
@@ -1653,8 +1666,9 @@ struct BatchBeam {
 
 constexpr int kBatchQueues = 8;
 // launch groups: 7 M_bin x 2 transfer-function forms, plus the three-pass
-// item's 4 downsampling factors x 2 forms at M_bin = 4096
-constexpr int kBatchGroups = 22;
+// item's 4 downsampling factors x 2 forms at M_bin = 4096, plus the radix-8
+// item (8 bins per lane) x 2 forms at M_bin = 2048 and 4096
+constexpr int kBatchGroups = 26;
 
 __global__ void batch_reset(unsigned long long *ctr, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -1662,13 +1676,15 @@ __global__ void batch_reset(unsigned long long *ctr, int n) {
 }
 
 // K >= 0: the M_bin = 4096 three-pass item (dm_item_x3) with ndec = 2^K
-template <int M, bool RECUR, int K = -1>
-__global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__ beams, int nbeam,
-                                                   long long total,
-                                                   unsigned long long *__restrict__ ctr) {
-    using Sh = FusedShape<M, 16>;
-    static_assert(Sh::WG == 256, "batched launches use 256-lane workgroups");
-    static_assert(K < 0 || M == 4096, "the three-pass item is built for M_bin = 4096");
+// R = 8: the radix-8 Stockham item (8 bins per lane; 512-lane workgroups at
+// M_bin = 4096, 256 at 2048)
+template <int M, bool RECUR, int K = -1, int R = 16>
+__global__ __launch_bounds__((FusedShape<M, R>::WG), (R == 8 ? 4 : 2)) void dm_batch(
+    const BatchBeam *__restrict__ beams, int nbeam, long long total,
+    unsigned long long *__restrict__ ctr) {
+    using Sh = FusedShape<M, R>;
+    static_assert(R == 8 || Sh::WG == 256, "radix-16 batched launches use 256-lane workgroups");
+    static_assert(K < 0 || (M == 4096 && R == 16), "the three-pass item is built for M_bin = 4096");
     __shared__ cpair sh[K >= 0 ? kX3Lds : Sh::C * Sh::STRIDE];
     __shared__ long long s_item;
     const int q = blockIdx.x % kBatchQueues;
@@ -1698,7 +1714,7 @@ __global__ __launch_bounds__(256, 2) void dm_batch(const BatchBeam *__restrict__
         if constexpr (K >= 0)
             dm_item_x3<RECUR, K>(a, MemDms{beams[b].dms}, dt, cg, sh);
         else
-            dm_item<M, 16, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
+            dm_item<M, R, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
     }
 }
 
@@ -2241,6 +2257,8 @@ struct cdmt_batch_s {
     std::vector<std::vector<double>> dms;     // host copies of the DM lists
     std::vector<size_t> spec_off;             // per beam: spectra in the workspace
     std::vector<int> fwd_n2;                  // per beam: forward split (0: the plan's)
+    std::vector<int> fft_sched;               // per beam: DM-stage schedule (-1: the plan's)
+    std::vector<int> lane_bins;               // per beam: bins per lane (0: the plan's)
     size_t dm_off = 0, tab_off = 0, ctr_off = 0;
     char *ws = nullptr;
     int device = 0;
@@ -2248,7 +2266,7 @@ struct cdmt_batch_s {
     int wg_per_cu = 2;
     long long total = 0;                      // work items over all launches
     struct Launch {
-        int m, recur, k, first, count;        // M_bin, form, three-pass K (-1: none),
+        int m, recur, k, r, first, count;     // M_bin, form, three-pass K (-1: none), bins per lane,
         long long items;                      // table rows [first, first + count)
     };
     std::vector<Launch> launches;             // one persistent launch per (M_bin, form)
@@ -2262,6 +2280,11 @@ namespace {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// channel chunks per workgroup of the batched DM-stage item
+int batch_chunks_per_wg(int m, int r) {
+    return r == 8 ? (m == 4096 ? FusedShape<4096, 8>::C : FusedShape<2048, 8>::C) : 4096 / m;
+}
+
 int batch_layout(const cdmt_beam_t *beams, int nbeam, std::vector<size_t> *spec_off,
                  size_t *dm_off, size_t *tab_off, size_t *ctr_off, size_t *total) {
     if (!beams || nbeam < 1 || nbeam > 4096)
@@ -2273,8 +2296,8 @@ int batch_layout(const cdmt_beam_t *beams, int nbeam, std::vector<size_t> *spec_
         const cdmt_plan_s *p = B.plan;
         if (!p || B.nblock < 1 || B.ndm < 1 || !B.voltages || !B.dm_list || !B.out)
             return CDMT_E_ARG;
-        if (p->precision != 0 || p->lane_bins != 16)
-            return CDMT_E_UNSUPPORTED;          // FP32, 16 bins per lane
+        if (p->precision != 0)
+            return CDMT_E_UNSUPPORTED;          // FP32
         if (p->m > 4096)
             return CDMT_E_UNSUPPORTED;          // 512-lane workgroups: use cdmt_dedisperse
         if ((long long)B.nblock * p->nsub * p->nchan > 0x7fffffffLL)
@@ -2312,7 +2335,7 @@ int batch_upload(cdmt_batch_s *bt) {
     bt->launches.clear();
     bt->total = 0;
     std::vector<BatchBeam> rows(nbeam);
-    std::vector<int> rec(nbeam), kk(nbeam);
+    std::vector<int> rec(nbeam), kk(nbeam), rr(nbeam);
     for (int b = 0; b < nbeam; ++b) {
         const cdmt_beam_t &B = bt->beams[b];
         const cdmt_plan_s *p = B.plan;
@@ -2320,7 +2343,9 @@ int batch_upload(cdmt_batch_s *bt) {
         std::memset(&T, 0, sizeof(T));
         T.a = fused_args(p, bt->ws + bt->spec_off[b], B.nblock, B.out);
         T.a.dm_tile = bt->dm_tile > 0 ? bt->dm_tile : p->dm_tile;
-        const int C = 4096 / p->m;              // chunks per 256-lane workgroup
+        const int lb = bt->lane_bins[b] ? bt->lane_bins[b] : p->lane_bins;
+        rr[b] = lb == 8 && (p->m == 2048 || p->m == 4096) ? 8 : 16;
+        const int C = batch_chunks_per_wg(p->m, rr[b]);
         T.a.inner = p->nchan >= C ? p->nchan / C : 1;
         T.a.ndm = B.ndm;
         T.a.ndt = (B.ndm + T.a.dm_tile - 1) / T.a.dm_tile;
@@ -2329,18 +2354,21 @@ int batch_upload(cdmt_batch_s *bt) {
                            arithmetic(d.data(), B.ndm, T.a.dm_step);
         T.a.dm_step = recur ? d[1] - d[0] : 0.0;
         rec[b] = recur ? 1 : 0;
-        kk[b] = p->m == 4096 ? x3_k(T.a) : -1;
+        if (bt->fft_sched[b] >= 0)
+            T.a.schedule = bt->fft_sched[b];
+        kk[b] = p->m == 4096 && rr[b] == 16 ? x3_k(T.a) : -1;
         T.dms = reinterpret_cast<const double *>(bt->ws + bt->dm_off) + dm_at[b];
     }
     for (int m = 64; m <= 4096; m *= 2) {
-        for (int r = 1; r >= 0; --r) {
-          for (int k = -1; k <= (m == 4096 ? 3 : -1); ++k) {
-            cdmt_batch_s::Launch L{m, r, k, (int)tab.size(), 0, 0};
+      for (int r = 1; r >= 0; --r) {
+        for (int R = 16; R >= 8; R -= 8) {
+          for (int k = -1; k <= (m == 4096 && R == 16 ? 3 : -1); ++k) {
+            cdmt_batch_s::Launch L{m, r, k, R, (int)tab.size(), 0, 0};
             for (int b = 0; b < nbeam; ++b) {
-                if (bt->beams[b].plan->m != m || rec[b] != r || kk[b] != k)
+                if (bt->beams[b].plan->m != m || rec[b] != r || kk[b] != k || rr[b] != R)
                     continue;
                 BatchBeam T = rows[b];
-                const int C = 4096 / m;
+                const int C = batch_chunks_per_wg(m, R);
                 T.item0 = L.items;
                 L.items += ((long long)T.a.nchunks + C - 1) / C * T.a.ndt;
                 tab.push_back(T);
@@ -2352,6 +2380,7 @@ int batch_upload(cdmt_batch_s *bt) {
             }
           }
         }
+      }
     }
     if (hipMemcpy(bt->ws + bt->dm_off, dmall.data(), dmall.size() * sizeof(double),
                   hipMemcpyHostToDevice) != hipSuccess)
@@ -2370,6 +2399,16 @@ void batch_launch(int recur, const BatchBeam *tab, int count, long long items,
         dm_batch<M, true><<<grid, 256, 0, st>>>(tab, count, items, ctr);
     else
         dm_batch<M, false><<<grid, 256, 0, st>>>(tab, count, items, ctr);
+}
+
+template <int M>
+void batch_launch8(int recur, const BatchBeam *tab, int count, long long items,
+                   unsigned long long *ctr, int grid, hipStream_t st) {
+    constexpr int WG = FusedShape<M, 8>::WG;
+    if (recur)
+        dm_batch<M, true, -1, 8><<<grid, WG, 0, st>>>(tab, count, items, ctr);
+    else
+        dm_batch<M, false, -1, 8><<<grid, WG, 0, st>>>(tab, count, items, ctr);
 }
 
 void batch_launch_x3(int recur, int k, const BatchBeam *tab, int count, long long items,
@@ -2417,6 +2456,15 @@ int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
         const BatchBeam *t = tab + L.first;
         if (L.k >= 0) {
             batch_launch_x3(L.recur, L.k, t, L.count, L.items, c, grid, st);
+            if (hipGetLastError() != hipSuccess)
+                return CDMT_E_DEVICE;
+            continue;
+        }
+        if (L.r == 8) {
+            if (L.m == 4096)
+                batch_launch8<4096>(L.recur, t, L.count, L.items, c, grid, st);
+            else
+                batch_launch8<2048>(L.recur, t, L.count, L.items, c, grid, st);
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
             continue;
@@ -2482,6 +2530,8 @@ int cdmt_batch_create(cdmt_batch_t *out, const cdmt_beam_t *beams, int nbeam, vo
     }
     bt->spec_off = off;
     bt->fwd_n2.assign(nbeam, 0);
+    bt->fft_sched.assign(nbeam, -1);
+    bt->lane_bins.assign(nbeam, 0);
     bt->dm_off = dm_off;
     bt->tab_off = tab_off;
     bt->ctr_off = ctr_off;
@@ -2529,21 +2579,51 @@ int cdmt_batch_get(cdmt_batch_t bt, int opt, long long *value) {
 }
 
 int cdmt_batch_beam_set(cdmt_batch_t bt, int beam, int opt, int value) {
-    if (!bt || beam < 0 || beam >= (int)bt->beams.size() || opt != CDMT_BATCH_BEAM_FWD_N2)
+    if (!bt || beam < 0 || beam >= (int)bt->beams.size())
         return CDMT_E_ARG;
-    if (value != 0 && !fwd_split_ok(bt->beams[beam].plan->nfft, value))
-        return CDMT_E_ARG;
-    bt->fwd_n2[beam] = value;
-    bt->dirty = true;
-    return CDMT_OK;
+    if (opt == CDMT_BATCH_BEAM_FWD_N2) {
+        if (value != 0 && !fwd_split_ok(bt->beams[beam].plan->nfft, value))
+            return CDMT_E_ARG;
+        bt->fwd_n2[beam] = value;
+        bt->dirty = true;
+        return CDMT_OK;
+    }
+    if (opt == CDMT_BATCH_BEAM_FFT_SCHEDULE || opt == CDMT_BATCH_BEAM_LANE_BINS) {
+        const bool sched = opt == CDMT_BATCH_BEAM_FFT_SCHEDULE;
+        if (sched ? (value < -1 || value > 1) : (value != 0 && value != 8 && value != 16))
+            return CDMT_E_ARG;
+        int &slot = sched ? bt->fft_sched[beam] : bt->lane_bins[beam];
+        if (slot == value)
+            return CDMT_OK;
+        // these decide the beam's launch group: rewrite the table
+        if (hipDeviceSynchronize() != hipSuccess)
+            return CDMT_E_DEVICE;
+        const int old = slot;
+        slot = value;
+        const int r = batch_upload(bt);
+        if (r)
+            slot = old;
+        return r;
+    }
+    return CDMT_E_ARG;
 }
-
 int cdmt_batch_beam_get(cdmt_batch_t bt, int beam, int opt, int *value) {
-    if (!bt || !value || beam < 0 || beam >= (int)bt->beams.size() ||
-        opt != CDMT_BATCH_BEAM_FWD_N2)
+    if (!bt || !value || beam < 0 || beam >= (int)bt->beams.size())
         return CDMT_E_ARG;
-    *value = bt->fwd_n2[beam] ? bt->fwd_n2[beam] : bt->beams[beam].plan->n2;
-    return CDMT_OK;
+    if (opt == CDMT_BATCH_BEAM_FWD_N2) {
+        *value = bt->fwd_n2[beam] ? bt->fwd_n2[beam] : bt->beams[beam].plan->n2;
+        return CDMT_OK;
+    }
+    if (opt == CDMT_BATCH_BEAM_FFT_SCHEDULE) {
+        *value = bt->fft_sched[beam] >= 0 ? bt->fft_sched[beam]
+                                          : bt->beams[beam].plan->fft_schedule;
+        return CDMT_OK;
+    }
+    if (opt == CDMT_BATCH_BEAM_LANE_BINS) {
+        *value = bt->lane_bins[beam] ? bt->lane_bins[beam] : bt->beams[beam].plan->lane_bins;
+        return CDMT_OK;
+    }
+    return CDMT_E_ARG;
 }
 
 int cdmt_batch_run(cdmt_batch_t bt, void *hip_stream) {
@@ -2627,6 +2707,45 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
         bt->fwd_n2[b] = fn2;
     }
     bt->dirty = true;
+    // the DM stage's radix schedule, per M_bin (the beams of one M_bin share
+    // its launches), each candidate timed on the whole batch with the other
+    // M_bin unchanged: at M_bin = 4096 the three-pass transform (schedule 0,
+    // where the beam allows it), radix-16 and radix-8 Stockham stages
+    // (schedule 1 with 16 or 8 bins per lane); at 2048 radix 16 or 8; other
+    // M_bin have the radix-16 stages only
+    for (int m = 2048; m <= 4096 && !r; m *= 2) {
+        std::vector<int> beams_m;
+        for (int b = 0; b < (int)bt->beams.size(); ++b)
+            if (bt->beams[b].plan->m == m)
+                beams_m.push_back(b);
+        if (beams_m.empty())
+            continue;
+        struct Cand { int sched, bins; };
+        const Cand cands[] = {{0, 16}, {1, 16}, {1, 8}};
+        float best_c = 0.f;
+        int pick = 0;
+        for (int ci = (m == 4096 ? 0 : 1); ci < 3 && !r; ++ci) {
+            for (int b : beams_m) {
+                bt->fft_sched[b] = cands[ci].sched;
+                bt->lane_bins[b] = cands[ci].bins;
+            }
+            if ((r = batch_upload(bt)))
+                break;
+            float ms = 0.f;
+            r = timed([&] { return batch_enqueue(bt, st); }, &ms);
+            if (!r && (best_c == 0.f || ms < best_c)) {
+                best_c = ms;
+                pick = ci;
+            }
+        }
+        if (!r) {
+            for (int b : beams_m) {
+                bt->fft_sched[b] = cands[pick].sched;
+                bt->lane_bins[b] = cands[pick].bins;
+            }
+            r = batch_upload(bt);
+        }
+    }
     static const int kTiles[] = {4, 8, 16};
     static const int kWg[] = {2, 4};
     float best = 0.f;

@@ -113,16 +113,18 @@ class BeamDraw:
 
 def batch_draws(nbeam: int = 24, seed: int = 1607) -> list:
     """Batched workload (several tied-array beams, Sec. 4): 32-288 subbands
-    inside 110-190 MHz, N_bin from {2^14, 2^15, 2^16, 2^17}, 16-256 DM trials
-    from 0 to a beam-specific maximum in [20, 200]."""
+    inside 110-190 MHz, N_bin from {2^14, 2^15, 2^16, 2^17}, channels so that
+    M_bin = N_bin / n_c is 1024, 2048 or 4096, 16-256 DM trials from 0 to a
+    beam-specific maximum in [20, 200]."""
     g = np.random.default_rng(np.random.SeedSequence([seed, 7331]))
     out = []
     for _ in range(nbeam):
         nsub = int(g.integers(32, 289))
         nfft = int(2 ** int(g.integers(14, 18)))
+        m = int(2 ** int(g.integers(10, 13)))
         half = nsub * SUBBAND_MHZ / 2
         f_centre = float(g.uniform(110.0 + half, 190.0 - half))
-        out.append(BeamDraw(nsub, f_centre, nfft, nfft // 4096, 8,
+        out.append(BeamDraw(nsub, f_centre, nfft, nfft // m, 8,
                             float(g.uniform(20.0, 200.0)), int(g.integers(16, 257))))
     return out
 

@@ -61,11 +61,12 @@ def _inputs(spec, seed):
     return cfg, v
 
 
-def _plan(hip_lib, spec, dm_tile=None, fwd_n2=None):
+def _plan(hip_lib, spec, dm_tile=None, fwd_n2=None, fft_schedule=None, lane_bins=None):
     return hip_lib.Plan(spec.nsub, spec.f_centre, synth.SUBBAND_MHZ, spec.nfft, spec.noverlap,
                         spec.nchan, spec.ndec,
                         input_kind=hip_lib.INPUT_CI8 if spec.kind == "ci8" else hip_lib.INPUT_CF32,
-                        chirp_ref=spec.chirp_ref, dm_tile=dm_tile, fwd_n2=fwd_n2)
+                        chirp_ref=spec.chirp_ref, dm_tile=dm_tile, fwd_n2=fwd_n2,
+                        fft_schedule=fft_schedule, lane_bins=lane_bins)
 
 
 def _setup(hip_lib, torch, specs):
@@ -81,8 +82,8 @@ def _setup(hip_lib, torch, specs):
     return beams, host
 
 
-def _single(hip_lib, sp, x, dm_tile, fwd_n2=None):
-    plan = _plan(hip_lib, sp, dm_tile, fwd_n2)
+def _single(hip_lib, sp, x, dm_tile, fwd_n2=None, fft_schedule=None, lane_bins=None):
+    plan = _plan(hip_lib, sp, dm_tile, fwd_n2, fft_schedule, lane_bins)
     return plan.dedisperse(x, sp.nblock, sp.dms)
 
 
@@ -173,29 +174,62 @@ def test_batch_graph_replays_and_autotune(hip_lib):
     assert torch.equal(beams[0][4], ref), "beam 0 with the 512 x 128 forward split"
     with pytest.raises(hip_lib.CdmtError):
         batch.beam_set(1, FN2, 512)               # not a split of 16384
+    # a per-beam DM-stage schedule: beam 0 (M_bin 4096, ndec 8) on the
+    # radix-16 Stockham stages instead of the three-pass transform
+    FS = hip_lib.CDMT_BATCH_BEAM_FFT_SCHEDULE
+    assert batch.beam_get(0, FS) == 0
+    nl = batch.get(hip_lib.CDMT_BATCH_LAUNCHES)
+    batch.beam_set(0, FS, 1)
+    assert batch.beam_get(0, FS) == 1
+    # beam 0 leaves the three-pass group (M_bin 4096, ndec 8) for a Stockham
+    # group of its own at M_bin 4096: the launch count stays the same
+    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == nl == 3
+    batch.run_graph(stream)
+    stream.synchronize()
+    ref = _single(hip_lib, specs[0], beams[0][2], None, 128, 1)
+    torch.cuda.synchronize()
+    assert torch.equal(beams[0][4], ref), "beam 0 on the Stockham schedule"
+    with pytest.raises(hip_lib.CdmtError):
+        batch.beam_set(0, FS, 2)
+    batch.beam_set(0, FS, -1)
+    # 8 bins per lane for beam 2 (M_bin 2048, radix-8 Stockham stages)
+    LB = hip_lib.CDMT_BATCH_BEAM_LANE_BINS
+    assert batch.beam_get(2, LB) == 16
+    batch.beam_set(2, LB, 8)
+    batch.run_graph(stream)
+    stream.synchronize()
+    ref = _single(hip_lib, specs[2], beams[2][2], None, None, None, 8)
+    torch.cuda.synchronize()
+    assert torch.equal(beams[2][4], ref), "beam 2 with 8 bins per lane"
+    with pytest.raises(hip_lib.CdmtError):
+        batch.beam_set(2, LB, 4)
+    batch.beam_set(2, LB, 0)
     best = batch.autotune(stream, reps=1)
     stream.synchronize()
     tile = batch.get(hip_lib.CDMT_BATCH_DM_TILE)
     wg = batch.get(hip_lib.CDMT_BATCH_WG_PER_CU)
     splits = [batch.beam_get(i, FN2) for i in range(len(specs))]
-    print(f"autotune: forward N2 {splits}, dm tile {tile}, {wg} workgroups per CU, "
-          f"{best:.3f} ms", flush=True)
+    scheds = [batch.beam_get(i, FS) for i in range(len(specs))]
+    bins = [batch.beam_get(i, LB) for i in range(len(specs))]
+    print(f"autotune: forward N2 {splits}, DM-stage schedules {scheds}, bins per lane {bins}, "
+          f"dm tile {tile}, {wg} workgroups per CU, {best:.3f} ms", flush=True)
     assert best > 0 and tile in (4, 8, 16) and wg in (2, 4)
     # after tuning (graph captured again) each beam equals its single run with
     # the chosen split and tile
     batch.run_graph(stream)
     stream.synchronize()
     for i, (sp, b) in enumerate(zip(specs, beams)):
-        ref = _single(hip_lib, sp, b[2], tile, splits[i])
+        ref = _single(hip_lib, sp, b[2], tile, splits[i], scheds[i], bins[i])
         torch.cuda.synchronize()
         assert torch.equal(b[4], ref), f"beam {i} after autotune"
 
 
 def test_batch_24_beam_workload(hip_lib):
-    """The benchmark's batched workload at full size (24 beams, ~125 GB), in
-    the benchmark's launch form (autotuned, graph replay): every output written
-    and finite, one (subband, block) pair per beam against the oracle, and two
-    beams bitwise equal to their single-beam runs."""
+    """The benchmark's batched workload at full size (24 beams, M_bin 1024,
+    2048 and 4096, 55 GB of filterbanks), in the benchmark's launch form
+    (autotuned, graph replay): every output written and finite, one
+    (subband, block) pair per beam against the oracle, and one beam of each
+    M_bin bitwise equal to its single-beam run with the tuned settings."""
     torch = _torch()
     import math
     from concurrent.futures import ThreadPoolExecutor
@@ -220,7 +254,9 @@ def test_batch_24_beam_workload(hip_lib):
         beams.append((plan, nblock, x, list(d.dms), out))
         cfgs.append((d, nov, nblock))
     batch = hip_lib.Batch(beams)
-    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == 1
+    # one persistent launch per M_bin present (every beam here takes the
+    # transfer-function recurrence and ndec 8)
+    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == len({d.nfft // d.nchan for d in draws}) > 1
     stream = torch.cuda.Stream()
     batch.autotune(stream, reps=1)
     batch.run_graph(stream)
@@ -246,11 +282,13 @@ def test_batch_24_beam_workload(hip_lib):
     print(f"batch workload vs oracle: worst beam {max(errs):.2e}", flush=True)
     assert max(errs) <= 1e-5
     tile = batch.get(hip_lib.CDMT_BATCH_DM_TILE)
-    for i in (0, len(beams) - 1):
+    for i in sorted({d.nfft // d.nchan: i for i, d in enumerate(draws)}.values()):
         d, nov, nblock = cfgs[i]
         plan = hip_lib.Plan(d.nsub, d.f_centre, synth.SUBBAND_MHZ, d.nfft, nov, d.nchan, d.ndec,
                             input_kind=hip_lib.INPUT_CI8, dm_tile=tile,
-                            fwd_n2=batch.beam_get(i, hip_lib.CDMT_BATCH_BEAM_FWD_N2))
+                            fwd_n2=batch.beam_get(i, hip_lib.CDMT_BATCH_BEAM_FWD_N2),
+                            fft_schedule=batch.beam_get(i, hip_lib.CDMT_BATCH_BEAM_FFT_SCHEDULE),
+                            lane_bins=batch.beam_get(i, hip_lib.CDMT_BATCH_BEAM_LANE_BINS))
         ref = plan.dedisperse(beams[i][2], nblock, list(d.dms))
         torch.cuda.synchronize()
         assert torch.equal(ref, beams[i][4]), f"beam {i} differs from its single-beam run"
