@@ -60,6 +60,8 @@ constexpr int kIncS = 4;                      // samples per lane, 64 apart
 constexpr int kIncT = 64 * kIncS;             // output samples per workgroup
 constexpr int kIncK = 12;                     // fine trials per workgroup (<= 16)
 constexpr int kIncSpan = 256;                 // widest delay spread staged in LDS
+constexpr int kIncW = 4;                      // trial groups (waves) sharing a staged window
+constexpr int kIncG = kIncW * kIncK;          // fine trials per shared-window workgroup
 
 // (both functions evaluate exactly as written, with no fused multiply-adds,
 // so that every rounding of a delay to whole samples is reproducible)
@@ -112,6 +114,45 @@ __global__ __launch_bounds__(256) void inc_delays(IncArgs a, IncDms dl, int firs
         for (int k = 1; k < kIncK; ++k)
             slot[k] = delay(k0 + k) - lo;
     }
+}
+
+// Delays for inc_sum_shared: per (DM, supergroup of kIncG trials, channel)
+// 16 words, the supergroup's first delay in word 0, then the offset of each
+// of its trials relative to it in bytes (trial k in byte k % 4 of word
+// 1 + k / 4), then in word 13 the largest offset (the window's extent),
+// laid out [d][supergroup][channel pair][32]; a missing second channel of an
+// odd count is all zero.
+__global__ __launch_bounds__(256) void inc_delays_shared(IncArgs a, IncDms dl, int first, int cnt,
+                                                         int *__restrict__ D) {
+#pragma clang fp contract(off)
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nsg = a.kpad / kIncG;
+    const long long per = (long long)a.nch * nsg;
+    if (i >= per * cnt)
+        return;
+    const int dl_i = (int)(i / per);
+    const int ch = (int)((i % per) / nsg);
+    const int k0 = (int)(i % nsg) * kIncG;
+    const auto delay = [&](int k) {
+        return (int)inc_delay(a, dl.dm[dl_i] + (a.ddm0 + a.ddm * (double)min(k, a.ntrial - 1)), ch);
+    };
+    const int lo = delay(k0);
+    const long long npair = (a.nch + 1) / 2;
+    int *slot = D + (((long long)(first + dl_i) * nsg + k0 / kIncG) * npair) * 32 + ch * 16;
+    unsigned b[kIncG / 4];
+    for (int q = 0; q < kIncG / 4; ++q)
+        b[q] = 0u;
+    for (int k = 1; k < kIncG; ++k)
+        b[k / 4] |= (unsigned)min(delay(k0 + k) - lo, kIncSpan - 1) << (8 * (k % 4));
+    slot[0] = lo;
+    for (int q = 0; q < kIncG / 4; ++q)
+        slot[1 + q] = (int)b[q];
+    for (int q = 1 + kIncG / 4; q < 16; ++q)
+        slot[q] = 0;
+    slot[1 + kIncG / 4] = min(delay(k0 + kIncG - 1) - lo, kIncSpan - 1);
+    if (ch == a.nch - 1 && a.nch % 2)
+        for (int q = 16; q < 32; ++q)
+            slot[q] = 0;
 }
 
 // TC channels x TT samples per tile, moved as float4 (nch and ntime
@@ -360,13 +401,153 @@ __global__ __launch_bounds__(64) void inc_sum(const float *__restrict__ ft,
     }
 }
 
+// inc_sum with one staged window shared by kIncW trial groups: a workgroup
+// of kIncW waves per (coherent DM, kIncG fine trials, kIncT output samples),
+// wave w summing trials 12 w .. 12 w + 11 of the supergroup exactly as
+// inc_sum<false> does (same additions in the same channel order, so the same
+// sums bit for bit).  Per channel pair the 256 lanes stage both channels'
+// windows (kIncT samples plus the supergroup's delay spread, below kIncSpan)
+// in LDS, two loads per lane and channel, loaded one pair ahead into
+// registers and stored into one of two buffers (one barrier per pair); the
+// pair's delays are wave-uniform scalar loads two pairs ahead.  Each window
+// is read from memory once per kIncG trials instead of once per kIncK.
+__global__ __launch_bounds__(64 * kIncW) void inc_sum_shared(const float *__restrict__ ft,
+                                                             const int *__restrict__ D, IncArgs a,
+                                                             int ntile, int nsg,
+                                                             float *__restrict__ out) {
+    constexpr int kWin = kIncT + kIncSpan;
+    static_assert(kWin == 2 * 64 * kIncW, "two window samples per lane and channel");
+    // two buffers, alternating by pair: a pair's windows are stored while the
+    // previous pair's are still being summed, one barrier per pair
+    __shared__ float win[2][2][kWin];
+    const int lw = xcd_remap(blockIdx.x, gridDim.x);
+    const int sgi = lw % nsg;
+    const int tile = (lw / nsg) % ntile;
+    const long long d = lw / ((long long)nsg * ntile);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int kg = sgi * kIncG + wv * kIncK;
+    const long long t0 = (long long)tile * kIncT;
+    float acc[kIncK][kIncS];
+#pragma unroll
+    for (int k = 0; k < kIncK; ++k)
+#pragma unroll
+        for (int j = 0; j < kIncS; ++j)
+            acc[k][j] = 0.f;
+    const int *dk = D + ((d * nsg + sgi) * ((a.nch + 1) / 2)) * 32;
+    const float *row = ft + d * a.nch * a.ntime + t0;
+    const int room = (int)(a.ntime - 1 - t0);
+    // a pair's delays as this wave needs them: both channels' first delay and
+    // the three words holding its own twelve offsets
+    struct Dl {
+        int lo[2], span[2];
+        int w[2][3];
+    };
+    const auto delays = [&](int p, Dl &r) {
+        const int *rec = dk + 32 * p;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            r.lo[c] = rec[16 * c];
+            r.span[c] = rec[16 * c + 1 + kIncG / 4];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                r.w[c][q] = rec[16 * c + 1 + 3 * wv + q];
+        }
+    };
+    const auto offset = [](const Dl &r, int c, int k) {
+        return (int)(((unsigned)r.w[c][k / 4] >> (8 * (k % 4))) & 0xffu);
+    };
+    // the window covers kIncT samples plus the supergroup's spread; loads
+    // past it fall outside the view and read 0 without touching memory
+    const auto fetch = [&](bool real, const float *r, int lo, int span, float (&pf)[2]) {
+        if (real) {
+            const auto v = inc_view(r + lo, min(room - lo + 1, kIncT + span));
+            pf[0] = inc_load(v, 4 * tid);
+            pf[1] = inc_load(v, 4 * (tid + 64 * kIncW));
+        } else {
+            pf[0] = pf[1] = 0.f;
+        }
+    };
+    const auto sums = [&](const Dl &dl, int buf) {
+        int held[2];
+        float w[2][kIncS];
+#pragma unroll
+        for (int k = 0; k < kIncK; ++k) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int o = offset(dl, c, k);
+                if (k == 0 || o != held[c]) {
+                    held[c] = o;
+#pragma unroll
+                    for (int j = 0; j < kIncS; ++j)
+                        w[c][j] = win[buf][c][lane + 64 * j + o];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+#pragma unroll
+                for (int j = 0; j < kIncS; ++j)
+                    inc_add(acc[k][j], w[c][j]);
+        }
+    };
+    const int npair = (a.nch + 1) / 2;
+    Dl dla, dlb, dlc;
+    float pf[2][2];
+    delays(0, dla);
+    if (npair > 1)
+        delays(1, dlb);
+    fetch(true, row, dla.lo[0], dla.span[0], pf[0]);
+    fetch(a.nch > 1, row + a.ntime, dla.lo[1], dla.span[1], pf[1]);
+    const auto pair = [&](int p, const Dl &cur, const Dl &nxt, Dl &far) {
+        // buffer p & 1 was last read for pair p - 2, which every wave summed
+        // before the previous pair's barrier
+        const int buf = p & 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            win[buf][c][tid] = pf[c][0];
+            win[buf][c][tid + 64 * kIncW] = pf[c][1];
+        }
+        row += 2 * a.ntime;
+        if (p + 1 < npair) {
+            fetch(true, row, nxt.lo[0], nxt.span[0], pf[0]);
+            fetch(2 * p + 3 < a.nch, row + a.ntime, nxt.lo[1], nxt.span[1], pf[1]);
+        }
+        if (p + 2 < npair)
+            delays(p + 2, far);
+        __syncthreads();
+        sums(cur, buf);
+    };
+    int p = 0;
+    for (; p + 2 < npair; p += 3) {
+        pair(p, dla, dlb, dlc);
+        pair(p + 1, dlb, dlc, dla);
+        pair(p + 2, dlc, dla, dlb);
+    }
+    if (p < npair)
+        pair(p, dla, dlb, dlc);
+    if (p + 1 < npair)
+        pair(p + 1, dlb, dlc, dla);
+    const int nk = min(kIncK, a.ntrial - kg);
+#pragma unroll
+    for (int k = 0; k < kIncK; ++k) {
+        if (k < nk) {
+            float *o = out + (d * a.ntrial + kg + k) * a.nout + t0 + lane;
+#pragma unroll
+            for (int j = 0; j < kIncS; ++j)
+                if (t0 + lane + 64 * j < a.nout)
+                    o[64 * j] = acc[k][j];
+        }
+    }
+}
+
 // Bound on the delay spread of kIncK consecutive trials in any channel: the
 // delay rint(c DM) of channel ch has c = k_DM u / tsamp, largest in the lowest
 // channel, so the spread is at most c_max (kIncK - 1) ddm + 1.
-bool inc_narrow(const IncArgs &a) {
+bool inc_narrow(const IncArgs &a, int ntrials = kIncK) {
     const double nu = inc_frequency(a, a.nch - 1), top = inc_frequency(a, 0);
     const double cmax = kKdm * (1.0 / (nu * nu) - 1.0 / (top * top)) / a.tsamp;
-    return cmax * (kIncK - 1) * a.ddm * (1.0 + 1e-9) + 2.0 < (double)kIncSpan;
+    return cmax * (ntrials - 1) * a.ddm * (1.0 + 1e-9) + 2.0 < (double)kIncSpan;
 }
 
 int inc_setup(const cdmt_plan_s *p, int nblock, const double *dm_coh, int ndm, double ddm0,
@@ -431,7 +612,10 @@ int cdmt_incoherent_workspace_size(cdmt_plan_t p, int nblock, int ndm, int ntria
     // channel-major already
     const size_t ft = p->out_layout ? 0 : (size_t)ndm * nch * ntime * sizeof(float);
     const size_t kpad = ((size_t)ntrial + kIncK - 1) / kIncK * kIncK;
-    *bytes = ((ft + 255) & ~(size_t)255) + (size_t)ndm * kpad * nch * sizeof(int);
+    const size_t nsg = ((size_t)ntrial + kIncG - 1) / kIncG;
+    const size_t table = std::max((size_t)ndm * kpad * nch,                 // [d][ch][k]
+                                  (size_t)ndm * nsg * ((nch + 1) / 2) * 32); // shared layout
+    *bytes = ((ft + 255) & ~(size_t)255) + table * sizeof(int);
     return CDMT_OK;
 }
 
@@ -458,15 +642,26 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
     const size_t ftb = chan_major ? 0 : (size_t)ndm * a.nch * a.ntime * sizeof(float);
     int *D = reinterpret_cast<int *>(static_cast<char *>(ws) + ((ftb + 255) & ~(size_t)255));
     const bool narrow = a.ntrial == 1 || inc_narrow(a);
+    // several trial groups share each staged window when there are more
+    // than one and the spread of kIncG trials fits the window
+    const bool shared = a.ntrial > kIncK && inc_narrow(a, kIncG);
+    IncArgs as = a;
+    as.kpad = (a.ntrial + kIncG - 1) / kIncG * kIncG;
+    const int nsg = as.kpad / kIncG;
     for (int first = 0; first < ndm; first += kIncDms) {
         const int cnt = ndm - first < kIncDms ? ndm - first : kIncDms;
         IncDms dl;
         std::memset(&dl, 0, sizeof(dl));
         for (int i = 0; i < cnt; ++i)
             dl.dm[i] = dm_coh[first + i];
-        const long long n = (long long)cnt * (a.kpad / kIncK) * a.nch;
-        inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt, narrow ? 1 : 0,
-                                                              D);
+        if (shared) {
+            const long long n = (long long)cnt * nsg * a.nch;
+            inc_delays_shared<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(as, dl, first, cnt, D);
+        } else {
+            const long long n = (long long)cnt * (a.kpad / kIncK) * a.nch;
+            inc_delays<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(a, dl, first, cnt,
+                                                                  narrow ? 1 : 0, D);
+        }
         if (hipGetLastError() != hipSuccess)
             return CDMT_E_DEVICE;
     }
@@ -485,6 +680,11 @@ int cdmt_incoherent(cdmt_plan_t p, int nblock, const float *fb, const double *dm
             return CDMT_E_DEVICE;
     }
     const int ntile = (int)((a.nout + kIncT - 1) / kIncT);
+    if (shared) {
+        const unsigned gs = (unsigned)((long long)ndm * ntile * nsg);
+        inc_sum_shared<<<gs, 64 * kIncW, 0, s>>>(ft, D, as, ntile, nsg, out);
+        return hipGetLastError() == hipSuccess ? CDMT_OK : CDMT_E_DEVICE;
+    }
     const int ngroup = a.kpad / kIncK;
     const unsigned grid = (unsigned)((long long)ndm * ntile * ngroup);
     if (narrow)

@@ -2,9 +2,16 @@
 the FP64 oracle, on M_bin = 4096 shapes (the LOFAR channel chunk).
 
 Bars: FP16x3 (11+11 significant bits per operand) is held to the FP32
-path's 1e-5 normwise bar.  BF16x3 (8+8 bits per operand, about 2^-16 per
-product) is stated at 2e-4 normwise, 1e-3 max-abs/max; both are checked so a
-regression shows, and the measured figures are printed."""
+path's 1e-5 normwise bar.  BF16x3: with u = 2^-8 (BF16's unit roundoff) a
+split operand x = hi + lo carries at most u^2 |x| of representation error and
+the dropped lo*lo product at most u^2 |a||b|, so each product in a radix-16
+stage is off by at most 3 u^2 relative, and a detected power after three
+stages by at most 2 * 3 * 3 u^2 = 2.7e-4 relative: the max-abs/max bar.  The
+per-product errors are rounding errors of random sign, about u^2 / sqrt(12)
+each (RMS); three such sources per product, three stages and the square give
+a normwise power error of at most about 2 sqrt(3) sqrt(3) u^2 / sqrt(12) =
+2.6e-5 (an estimate with every source at full strength); the normwise bar is
+5e-5 (measured 3.5e-6).  The measured figures are printed."""
 import numpy as np
 import pytest
 
@@ -13,7 +20,7 @@ from paper_1607_00909_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-BARS = {1: (2e-4, 1e-3), 2: (1e-5, 1e-5)}
+BARS = {1: (5e-5, 2.7e-4), 2: (1e-5, 1e-5)}
 NAMES = {1: "bf16x3", 2: "fp16x3"}
 
 
