@@ -467,7 +467,7 @@ def incoherent_leg(cdmt, torch, plan, w, out, dms, steps: int):
     tsamp = w.nchan * w.ndec / (w.bw * 1e6)
     adds = len(dm_coh) * ntrial * nout * nch
     adds_peak = 256 * 128 * 2.4e9                # FP32 adds per second (128 lanes per CU per clock)
-    traffic = measured_traffic("inc_sum<false>", PROFILE_INC, ("incoherent.hip", "plan.hpp"))
+    traffic = measured_traffic("inc_sum_shared", PROFILE_INC, ("incoherent.hip", "plan.hpp"))
     del iws, iout
     return {"ms": round(ms, 3), "ms_channel_major_input": round(ms_cm, 3),
             "channel_major_identical": same, "coherent_dms": len(dm_coh), "fine_trials": ntrial,
