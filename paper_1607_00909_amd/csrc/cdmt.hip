@@ -1333,7 +1333,11 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
 // 256 q, which is the bin the lane loaded into register q ^ 8 (the swap of
 // halves).  The per-bin terms Re(conj(g_S') i S') g2 are summed in FP64.
 // Exchange B writes into the slots its own wave read in exchange A, so the
-// next DM's exchange 1 needs no barrier: three barriers per DM.
+// next DM's exchange 1 needs no barrier: three barriers per DM.  The lane's
+// bins of the spectrum stay in registers for the whole DM tile (they do not
+// depend on the DM); the transfer function is evaluated twice per DM, for the
+// forward transform and for the final product, which costs less than
+// re-reading the spectrum from L2 each DM.
 constexpr int kGradTile = 16;
 
 template <int TILE>
@@ -1418,24 +1422,31 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         }
     };
 
+    // the lane's 16 bins of the spectrum, loaded once for the whole DM tile
+    cpair xs[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+        xs[q] = __builtin_bit_cast(
+            cpair, __builtin_amdgcn_raw_buffer_load_b128(spec_view, lane_off, 4096 * q, 0));
+    // the exact transfer function of bin q at this DM (Eq. 1), evaluated at
+    // the start of the DM and again for the final product rather than held
+    auto chirp = [&](double dm, int q) {
+        const double ph = dm * g2[q];
+        const double n = rint(ph);
+        float sn, cs;
+        sincos_pi(static_cast<float>(ph - n), sn, cs);
+        const int flip = static_cast<int>(n) << 31;
+        return make_float2(__int_as_float(__float_as_int(cs) ^ flip),
+                           __int_as_float(__float_as_int(sn) ^ flip));
+    };
+
     for (int d = d0; d < d1; ++d) {
         const double dm = dl.dm[d];
-        // the chirped spectrum S' of this DM, held for the final product
-        cpair sp[16], v[16];
+        // the chirped spectrum S' of this DM
+        cpair v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const double ph = dm * g2[q];
-            const double n = rint(ph);
-            float sn, cs;
-            sincos_pi(static_cast<float>(ph - n), sn, cs);
-            const int flip = static_cast<int>(n) << 31;
-            const float2 h = make_float2(__int_as_float(__float_as_int(cs) ^ flip),
-                                         __int_as_float(__float_as_int(sn) ^ flip));
-            const cpair x = __builtin_bit_cast(
-                cpair, __builtin_amdgcn_raw_buffer_load_b128(spec_view, lane_off, 4096 * q, 0));
-            sp[q] = cdmt::pmul(x, h);
-            v[q ^ 8] = sp[q];
-        }
+        for (int q = 0; q < 16; ++q)
+            v[q ^ 8] = cdmt::pmul(xs[q], chirp(dm, q));
         // y: pass 1, exchange 1 (within the wave), pass 2, exchange 2
         cdmt::dft16<+1>(v);
         twiddle(v, r1, false);
@@ -1490,12 +1501,16 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
             v[r] = x1r[r];
         twiddle(v, r2b, true);
         cdmt::dft16<-1>(v);
-        // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols
+        // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols; the
+        // DM is passed through an empty asm so that the compiler evaluates the
+        // transfer function here again instead of holding the first one
+        double dmr = dm;
+        asm volatile("" : "+s"(dmr));
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             const cpair gz = v[q ^ 8];
-            const cpair x = sp[q];
+            const cpair x = cdmt::pmul(xs[q], chirp(dmr, q));
             const float tx = gz.y * x.x - gz.x * x.y;
             const float ty = gz.w * x.z - gz.z * x.w;
             acc = fma(g2[q], (double)tx + (double)ty, acc);

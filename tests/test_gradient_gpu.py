@@ -58,13 +58,17 @@ def _oracle_gradient(cfg, v, nblock, dms, G):
 CASES = [  # nsub, f_centre, nfft, noverlap, nchan, ndec, nblock, mode, kind
     (4, 120.0, 16384, 4096, 8, 4, 2, oracle.CHANNEL, "cf32"),
     (4, 120.0, 16384, 4096, 8, 4, 2, oracle.SUBBAND, "cf32"),
+    # M_bin 4096: blocks of 448, 896 and 1792 output samples (G rows staged
+    # through LDS two or four samples per lane, or loaded directly)
     (2, 140.0, 65536, 8192, 16, 8, 2, oracle.CHANNEL, "ci8"),
+    (2, 140.0, 65536, 8192, 16, 4, 2, oracle.CHANNEL, "cf32"),
+    (2, 140.0, 65536, 8192, 16, 2, 2, oracle.SUBBAND, "ci8"),
     (3, 150.0, 8192, 2048, 32, 2, 3, oracle.SUBBAND, "ci8"),
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"M{c[2] // c[4]}-{'sub' if c[7] else 'chan'}-{c[8]}"
-                                             for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"M{c[2] // c[4]}-ndec{c[5]}-{'sub' if c[7] else 'chan'}"
+                                             f"-{c[8]}" for c in CASES])
 def test_dm_gradient_matches_oracle(hip_lib, case):
     torch = _torch()
     nsub, fc, nfft, nov, nchan, ndec, nblock, mode, kind = case
