@@ -501,6 +501,7 @@ __device__ __align__(16) float2 g_tw2[256 * 16];
 
 constexpr int kX3Region = 4 * 16 * 17;       // bin pairs of LDS per wave
 constexpr int kX3Lds = 4 * kX3Region;        // per workgroup (68 KiB)
+constexpr int kX3TwLds = 16 * 18 / 2;        // pass 2's twiddle table in LDS, rows of 18 float2
 
 // x from lane (lane xor the DPP pattern): quad_perm [1,0,3,2] = lane ^ 1,
 // [2,3,0,1] = lane ^ 2, row_half_mirror = lane ^ 7 within 8 lanes
@@ -533,7 +534,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 // One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
 // (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
-template <bool RECUR, int K, class DMS>
+template <bool RECUR, int K, class DMS, bool TWL = false>
 __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
     constexpr int M = 4096;
     const int L = threadIdx.x;
@@ -594,7 +595,18 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             tw2[2 * h + 1] = make_float2(x.z, x.w);
         }
     }
-    const float4 *row1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
+    // pass 2's twiddle row G1: from L1, or (TWL: sh holds kX3TwLds more bin
+    // pairs) from a copy of the table in LDS, rows 144 bytes apart so that the
+    // 16 rows' 16-byte reads fall on distinct bank groups
+    const float4 *row1;
+    if constexpr (TWL) {
+        float2 *const twl = reinterpret_cast<float2 *>(sh + kX3Lds);
+        twl[18 * (L >> 4) + (L & 15)] = g_tw1[L];
+        __syncthreads();
+        row1 = reinterpret_cast<const float4 *>(twl + 18 * l03);
+    } else {
+        row1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
+    }
 
     // LDS: exchange 1 writes at xw + 17 k (row k of 17 slots, column l03 of
     // block (w, l45)) and reads at x1r + r (row l03, column r); exchange 2
@@ -755,13 +767,15 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
 
 template <bool RECUR, int K>
 __global__ __launch_bounds__(256, 2) void fused_dedisperse_x3(FusedArgs a, DmList dl) {
-    __shared__ cpair sh[kX3Lds];
+    __shared__ cpair sh[kX3Lds + kX3TwLds];
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
     const int ci = lw % a.inner;
     const int rest = lw / a.inner;
     const int dt = rest % a.ndt;
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
-    dm_item_x3<RECUR, K>(a, ArgDms{dl}, dt, cg, sh);
+    // the LDS twiddle table at ndec = 8 (measured 1.4% faster there; at
+    // smaller ndec its registers would spill)
+    dm_item_x3<RECUR, K, ArgDms, K == 3>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
