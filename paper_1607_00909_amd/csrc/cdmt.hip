@@ -1366,7 +1366,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
                                                      double *__restrict__ part, long long ncg_all,
                                                      int dm_first) {
     constexpr int M = 4096;
-    __shared__ cpair sh[kX3Lds];
+    __shared__ cpair sh[kX3Lds + kX3TwLds];
     __shared__ double red[4][TILE];
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
     const int ci = lw % a.inner;
@@ -1411,9 +1411,14 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
     cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
     const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
     cpair *const x2 = sh + 16 * (L >> 4) + l03;
-    const float4 *const r1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
+    // the w256 twiddle table (rows G1 forward, J0 adjoint) as a padded copy in
+    // LDS, as in dm_item_x3; the w4096 rows are read through L1
+    float2 *const twl = reinterpret_cast<float2 *>(sh + kX3Lds);
+    twl[18 * (L >> 4) + (L & 15)] = g_tw1[L];
+    __syncthreads();
+    const float4 *const r1 = reinterpret_cast<const float4 *>(twl + 18 * l03);
     const float4 *const r2 = reinterpret_cast<const float4 *>(g_tw2 + 16 * L);
-    const float4 *const r1b = reinterpret_cast<const float4 *>(g_tw1 + 16 * (L >> 4));
+    const float4 *const r1b = reinterpret_cast<const float4 *>(twl + 18 * (L >> 4));
     const float4 *const r2b =
         reinterpret_cast<const float4 *>(g_tw2 + 16 * ((L >> 4) + 16 * l03));
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
