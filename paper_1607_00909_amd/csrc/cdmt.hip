@@ -501,7 +501,21 @@ __device__ __align__(16) float2 g_tw2[256 * 16];
 
 constexpr int kX3Region = 4 * 16 * 17;       // bin pairs of LDS per wave
 constexpr int kX3Lds = 4 * kX3Region;        // per workgroup (68 KiB)
-constexpr int kX3TwLds = 16 * 18 / 2;        // pass 2's twiddle table in LDS, rows of 18 float2
+constexpr int kX3TwLds = 4 * 144;            // pass 2's twiddle table in LDS (four copies)
+
+// The w256 twiddle table g_tw1 (row r, column c: exp(+2 pi i r c / 256)) as
+// four copies in LDS, 16-byte slot 144 k + 16 h + r of copy k holding
+// columns 2h, 2h + 1 of row r.  A wave whose lane L reads row L & 15 from copy
+// (L >> 4) & 3 touches 64 distinct slots mod 64 per read (no bank conflicts;
+// one copy with the 64 lanes' reads of 16 rows broadcast to 4 lanes each
+// measured 0.112 conflict cycles per LDS-active cycle).  All 256 lanes write.
+__device__ __forceinline__ void put_tw1_lds(float2 *twl) {
+    const int L = threadIdx.x, r = L >> 4, c = L & 15;
+    const float2 t = g_tw1[L];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        twl[2 * (144 * k + 16 * (c >> 1) + r) + (c & 1)] = t;
+}
 
 // x from lane (lane xor the DPP pattern): quad_perm [1,0,3,2] = lane ^ 1,
 // [2,3,0,1] = lane ^ 2, row_half_mirror = lane ^ 7 within 8 lanes
@@ -595,15 +609,14 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             tw2[2 * h + 1] = make_float2(x.z, x.w);
         }
     }
-    // pass 2's twiddle row G1: from L1, or (TWL: sh holds kX3TwLds more bin
-    // pairs) from a copy of the table in LDS, rows 144 bytes apart so that the
-    // 16 rows' 16-byte reads fall on distinct bank groups
+    // pass 2's twiddle row G1, columns 2h, 2h + 1 at row1[TWS h]: from L1, or
+    // (TWL: sh holds kX3TwLds more bin pairs) from the LDS copies
     const float4 *row1;
+    constexpr int TWS = TWL ? 16 : 1;
     if constexpr (TWL) {
-        float2 *const twl = reinterpret_cast<float2 *>(sh + kX3Lds);
-        twl[18 * (L >> 4) + (L & 15)] = g_tw1[L];
+        put_tw1_lds(reinterpret_cast<float2 *>(sh + kX3Lds));
         __syncthreads();
-        row1 = reinterpret_cast<const float4 *>(twl + 18 * l03);
+        row1 = reinterpret_cast<const float4 *>(sh + kX3Lds) + 144 * l45 + l03;
     } else {
         row1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
     }
@@ -665,7 +678,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         float2 tw1[16];
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
-            const float4 x = row1[h];
+            const float4 x = row1[TWS * h];
             tw1[2 * h] = make_float2(x.x, x.y);
             tw1[2 * h + 1] = make_float2(x.z, x.w);
         }
@@ -773,7 +786,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_x3(FusedArgs a, DmLis
     const int rest = lw / a.inner;
     const int dt = rest % a.ndt;
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
-    // the LDS twiddle table at ndec = 8 (measured 1.4% faster there; at
+    // the LDS twiddle table at ndec = 8 (measured 2.3% faster there; at
     // smaller ndec its registers would spill)
     dm_item_x3<RECUR, K, ArgDms, K == 3>(a, ArgDms{dl}, dt, cg, sh);
 }
@@ -1411,14 +1424,15 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
     cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
     const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
     cpair *const x2 = sh + 16 * (L >> 4) + l03;
-    // the w256 twiddle table (rows G1 forward, J0 adjoint) as a padded copy in
-    // LDS, as in dm_item_x3; the w4096 rows are read through L1
-    float2 *const twl = reinterpret_cast<float2 *>(sh + kX3Lds);
-    twl[18 * (L >> 4) + (L & 15)] = g_tw1[L];
+    // the w256 twiddle table (rows G1 forward, J0 adjoint) from its LDS copies,
+    // as in dm_item_x3 (slot stride 16 between column pairs); the w4096 rows
+    // are read through L1 (stride 1)
+    put_tw1_lds(reinterpret_cast<float2 *>(sh + kX3Lds));
     __syncthreads();
-    const float4 *const r1 = reinterpret_cast<const float4 *>(twl + 18 * l03);
+    const float4 *const twq = reinterpret_cast<const float4 *>(sh + kX3Lds);
+    const float4 *const r1 = twq + 144 * l45 + l03;
     const float4 *const r2 = reinterpret_cast<const float4 *>(g_tw2 + 16 * L);
-    const float4 *const r1b = reinterpret_cast<const float4 *>(twl + 18 * (L >> 4));
+    const float4 *const r1b = twq + 144 * (l03 & 3) + (L >> 4);
     const float4 *const r2b =
         reinterpret_cast<const float4 *>(g_tw2 + 16 * ((L >> 4) + 16 * l03));
     const int col = (a.nsub - 1 - s) * a.nchan + (a.nchan - 1 - c);
@@ -1436,10 +1450,10 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
     }
 
     // twiddle multiply from a row of 8 float4 (conjugated for the adjoint)
-    auto twiddle = [](cpair (&v)[16], const float4 *row, bool conj) {
+    auto twiddle = [](cpair (&v)[16], const float4 *row, int stride, bool conj) {
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
-            const float4 x = row[h];
+            const float4 x = row[stride * h];
             const float sy = conj ? -1.f : 1.f;
             if (h > 0)
                 v[2 * h] = cdmt::pmul(v[2 * h], make_float2(x.x, sy * x.y));
@@ -1474,7 +1488,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
             v[q ^ 8] = cdmt::pmul(xs[q], chirp(dm, q));
         // y: pass 1, exchange 1 (within the wave), pass 2, exchange 2
         cdmt::dft16<+1>(v);
-        twiddle(v, r1, false);
+        twiddle(v, r1, 16, false);
 #pragma unroll
         for (int k = 0; k < 16; ++k)
             xw[17 * k] = v[k];
@@ -1491,7 +1505,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             v[r] = x2[kX3Region * (r >> 2) + 272 * (r & 3)];
-        twiddle(v, r2, false);
+        twiddle(v, r2, 1, false);
         cdmt::dft16<+1>(v);
         // g_y = 2 G y on the kept samples m = L + 256 q
         const float *g = gout + (long long)d * a.ntime_out * a.nch_out +
@@ -1505,7 +1519,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         }
         // g_x: pass 1 (e-), exchange A (across the waves)
         cdmt::dft16<-1>(v);
-        twiddle(v, r1b, true);
+        twiddle(v, r1b, 16, true);
         __syncthreads();                   // every wave has read exchange 2
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1524,7 +1538,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             v[r] = x1r[r];
-        twiddle(v, r2b, true);
+        twiddle(v, r2b, 1, true);
         cdmt::dft16<-1>(v);
         // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols; the
         // DM is passed through an empty asm so that the compiler evaluates the
