@@ -107,6 +107,9 @@ CASES = [
     (3, 16384, 1024, 16, 3, 2, "cf32", oracle.CHANNEL, -1, 6, 2),    # M = 1024, ndec 3
     (1, 32768, 8192, 8, 8, 2, "ci8", oracle.SUBBAND, -1, 9, 4),      # M = 4096, nfft 2^15
     (2, 65536, 15360, 16, 8, 2, "ci8", oracle.CHANNEL, -1, 9, 4),    # LOFAR chunk shape
+    (1, 65536, 8192, 16, 1, 2, "cf32", oracle.CHANNEL, -1, 5, 4),    # M = 4096, ndec 1
+    (1, 65536, 8192, 16, 2, 2, "ci8", oracle.SUBBAND, 1, 5, 3),      # M = 4096, ndec 2
+    (1, 65536, 8192, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 6, 16),   # M = 4096, ndec 4
     (2, 65536, 15360, 16, 8, 2, "ci8", oracle.SUBBAND, -1, 9, 8, 8), # same, 8 bins per lane
     (1, 32768, 4096, 16, 2, 2, "cf32", oracle.CHANNEL, 1, 5, 2, 8),  # M = 2048, 8 bins per lane
     (1, 131072, 16384, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 3, 1),  # M = 8192, nfft 2^17
@@ -116,8 +119,8 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"M{c[1] // c[3]}-nfft{c[1]}-{c[6]}-b{(c + (16,))[11]}"
-                                             for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"M{c[1] // c[3]}-nfft{c[1]}-ndec{c[4]}-{c[6]}"
+                                             f"-b{(c + (16,))[11]}" for c in CASES])
 def test_shapes_parity(hip_lib, case):
     nsub, nfft, nov, nchan, ndec, nblock, kind, ref_mode, sign, ndm, tile = case[:11]
     bins = case[11] if len(case) > 11 else 16

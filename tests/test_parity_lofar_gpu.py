@@ -97,8 +97,9 @@ def test_lofar_full_size_sampled_parity(hip_lib):
     assert bool(torch.equal(out_c.transpose(1, 2), out_b))
     del out_c
     # the split-precision DM stages at full size (FP16x3 held to the FP32 bar;
-    # BF16x3 to its stated 2e-4 normwise, 1e-3 max-abs/max)
-    for prec, label, bars in ((2, "fp16x3", (1e-5, 1e-5)), (1, "bf16x3", (2e-4, 1e-3))):
+    # BF16x3 to the bars derived from its split error in
+    # test_parity_mixed_gpu: 5e-5 normwise, 2.7e-4 max-abs/max)
+    for prec, label, bars in ((2, "fp16x3", (1e-5, 1e-5)), (1, "bf16x3", (5e-5, 2.7e-4))):
         out_c = run(precision=prec)
         assert bool(torch.isfinite(out_c).all())
         _check_pairs(out_c, w, label, *bars)
