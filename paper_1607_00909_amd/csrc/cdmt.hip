@@ -498,6 +498,8 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
 // lane index).  Filled once per device from double precision.
 __device__ __align__(16) float2 g_tw1[16 * 16];
 __device__ __align__(16) float2 g_tw2[256 * 16];
+// M_bin = 2048 pass 3: row l (0..127), column r: exp(+2 pi i (r & 7)(l + 128 (r >> 3)) / 2048)
+__device__ __align__(16) float2 g_tw2h[128 * 16];
 
 constexpr int kX3Region = 4 * 16 * 17;       // bin pairs of LDS per wave
 constexpr int kX3Lds = 4 * kX3Region;        // per workgroup (68 KiB)
@@ -548,31 +550,41 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 // One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
 // (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
-template <bool RECUR, int K, class DMS, bool TWL = false>
+template <bool RECUR, int K, class DMS, bool TWL = false, int M = 4096>
 __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
-    constexpr int M = 4096;
+    static_assert(M == 4096 || M == 2048, "three-pass schedules: 16 x 16 x 16 and 16 x 16 x 8");
+    // M = 4096: one chunk per workgroup; M = 2048: two, chunk f on waves
+    // 2f, 2f + 1 (a second chunk past the end runs on zeros, stores nothing)
+    constexpr int LC = M / 16;            // lanes per chunk
     const int L = threadIdx.x;
-    const int chunk = cg;
-    const int c = chunk % a.nchan;
-    const int bs = chunk / a.nchan;
+    // the chunk index is uniform over a wave: kept scalar (readfirstlane)
+    const int f = M == 4096 ? 0 : __builtin_amdgcn_readfirstlane(L / LC);
+    const int Lc = M == 4096 ? L : L % LC;
+    const int chunk = M == 4096 ? cg : cg * (4096 / M) + f;
+    const bool valid = M == 4096 || chunk < a.nchunks;   // one chunk: always in range
+    const int cc = valid ? chunk : 0;
+    const int c = cc % a.nchan;
+    const int bs = cc / a.nchan;
     const int s = bs % a.nsub;
     const int b = bs / a.nsub;
     const int w = L >> 6, l45 = (L >> 4) & 3, l03 = L & 15;
+    const int wc = w % (LC / 64);         // wave within the chunk
 
-    // bins G0 + 16 G1 + 256 q (G0 = l45 + 4 w, G1 = l03), both pols,
-    // increasing frequency; the transform input index is bin ^ 2048
-    const int base = l45 + 4 * w + 16 * l03;
+    // bins G0 + LC/16 G1 + LC q (G0 = l45 + 4 wc, G1 = l03), both pols,
+    // increasing frequency; the transform input index is bin ^ (M / 2)
+    const int base = l45 + 4 * wc + (LC / 16) * l03;
     cpair raw[16];
     {
-        // the chunk as a raw buffer (uniform descriptor), row q at a scalar
-        // offset of 4096 q bytes from this lane's 32-bit offset
+        // the chunk as a raw buffer (uniform descriptor; no records for a
+        // chunk past the end), row q at a scalar offset of 16 LC q bytes from
+        // this lane's 32-bit offset
         const cpair *chunk = a.spec + (long long)bs * a.n + (long long)c * M;
         const __amdgpu_buffer_rsrc_t view = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<cpair *>(chunk), (short)0, M * 16, 0x00020000);
+            const_cast<cpair *>(chunk), (short)0, valid ? M * 16 : 0, 0x00020000);
 #pragma unroll
         for (int q = 0; q < 16; ++q)
             raw[q] = __builtin_bit_cast(
-                cpair, __builtin_amdgcn_raw_buffer_load_b128(view, 16 * base, 4096 * q, 0));
+                cpair, __builtin_amdgcn_raw_buffer_load_b128(view, 16 * base, 16 * LC * q, 0));
     }
 
     // DM-independent part of Eq. 1 per bin (as in dm_item)
@@ -594,14 +606,14 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
     for (int q = 0; q < 16; ++q) {
         // (the bin's index converted per item: a per-lane constant held
         // across a batch's items would cost 32 registers)
-        const double nu = ((double)(base + 256 * q + cofs) + off) * a.delta;
+        const double nu = ((double)(base + LC * q + cofs) + off) * a.delta;
         g2[q] = scale * nu * nu / (nu0 + nu);
     }
 
-    // pass 3's twiddles (DM-invariant): row L
+    // pass 3's twiddles (DM-invariant): row Lc of the M_bin's table
     float2 tw2[16];
     {
-        const float4 *row = reinterpret_cast<const float4 *>(g_tw2 + 16 * L);
+        const float4 *row = reinterpret_cast<const float4 *>((M == 4096 ? g_tw2 : g_tw2h) + 16 * Lc);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             const float4 x = row[h];
@@ -623,13 +635,19 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
 
     // LDS: exchange 1 writes at xw + 17 k (row k of 17 slots, column l03 of
     // block (w, l45)) and reads at x1r + r (row l03, column r); exchange 2
-    // writes at xw + 16 k (rows of 16) and reads at x2r + kX3Region (r >> 2) +
-    // 272 (r & 3) (block G0 = r, row L >> 4, column l03).  The block pitch
-    // (272 = 16 mod 64 slots) and the row pitches keep all 64 lanes of a wave
-    // on distinct 16-byte bank groups of 64 banks in every access.
+    // writes at xw + 16 k (rows of 16) and reads at x2r + x2off(r): at
+    // M = 4096 block G0 = r of the workgroup's regions, row L >> 4 = K1,
+    // column l03 = K0; at M = 2048 block G0 = r & 7 of the chunk's two
+    // regions, row (Lc >> 4) + 8 (r >> 3) = K1.  The block pitch (272 = 16
+    // mod 64 slots) and the row pitches keep all 64 lanes of a wave on
+    // distinct 16-byte slots mod 64 in every access.
     cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
     const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
-    const cpair *const x2r = sh + 16 * (L >> 4) + l03;
+    const cpair *const x2r = sh + (LC / 64) * f * kX3Region + Lc;
+    auto x2off = [](int r) {
+        return M == 4096 ? kX3Region * (r >> 2) + 272 * (r & 3)
+                         : kX3Region * ((r >> 2) & 1) + 272 * (r & 3) + 128 * (r >> 3);
+    };
 
     // output: this lane's samples after the sum over lane bits 0..K-1; column
     // of the channel in decreasing frequency
@@ -710,14 +728,22 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         __builtin_amdgcn_s_setprio(1);
 #pragma unroll
         for (int r = 0; r < 16; ++r)
-            v[r] = x2r[kX3Region * (r >> 2) + 272 * (r & 3)];
-        // pass 3
+            v[r] = x2r[x2off(r)];
+        // pass 3 (at M = 2048 two DFT-8 over registers r & 7, r >> 3 fixed;
+        // tw2 is 1 at r = 0 and, for M = 2048, at r = 8)
 #pragma unroll
         for (int r = 1; r < 16; ++r)
-            v[r] = cdmt::pmul(v[r], tw2[r]);
-        cdmt::dft16<+1>(v);
+            if (M == 4096 || r != 8)
+                v[r] = cdmt::pmul(v[r], tw2[r]);
+        if constexpr (M == 4096) {
+            cdmt::dft16<+1>(v);
+        } else {
+            cdmt::dft8<+1>(v);
+            cdmt::dft8<+1>(v + 8);
+        }
 
-        // detection: register q holds sample L + 256 q
+        // detection: register q holds sample Lc + LC (q >> 3) + 256 (q & 7)
+        // (at M = 4096: Lc + 256 q)
         float p[16];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
@@ -749,7 +775,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         }
         // first summed sample m of value r, then the filterbank sample
         // (m - n_d / 2) / ndec if it is kept
-        const int mlane = L & ~((1 << K) - 1);
+        const int mlane = Lc & ~((1 << K) - 1);
         float *out = a.out + (long long)d * a.ntime_out * a.nch_out +
                      (long long)b * a.tblk * a.t_stride + col * a.col_stride;
 #pragma unroll
@@ -759,9 +785,9 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             else if constexpr (K == 1) q = 2 * r + (L & 1);
             else if constexpr (K == 2) q = 4 * r + 2 * ((L >> 1) & 1) + (L & 1);
             else q = 8 * r + 4 * ((L >> 1) & 1) + 2 * (L & 1) + ((L >> 2) & 1);
-            const int m = mlane + 256 * q;
+            const int m = mlane + (M == 4096 ? 256 * q : LC * (q >> 3) + 256 * (q & 7));
             const int tq = (m - a.nd_half) >> K;
-            if (m >= a.nd_half && tq < a.tblk)
+            if (valid && m >= a.nd_half && tq < a.tblk)
                 out[(long long)tq * a.t_stride] = o[r];
         }
     };
@@ -778,7 +804,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
     }
 }
 
-template <bool RECUR, int K>
+template <bool RECUR, int K, int M = 4096>
 __global__ __launch_bounds__(256, 2) void fused_dedisperse_x3(FusedArgs a, DmList dl) {
     __shared__ cpair sh[kX3Lds + kX3TwLds];
     const int lw = xcd_remap(blockIdx.x, gridDim.x);
@@ -788,7 +814,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_x3(FusedArgs a, DmLis
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
     // the LDS twiddle table at ndec = 8 (measured 2.3% faster there; at
     // smaller ndec its registers would spill)
-    dm_item_x3<RECUR, K, ArgDms, K == 3>(a, ArgDms{dl}, dt, cg, sh);
+    dm_item_x3<RECUR, K, ArgDms, K == 3, M>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1729,7 +1755,7 @@ __global__ void batch_reset(unsigned long long *ctr, int n) {
         ctr[i] = 0;
 }
 
-// K >= 0: the M_bin = 4096 three-pass item (dm_item_x3) with ndec = 2^K
+// K >= 0: the three-pass item (dm_item_x3, M_bin 4096 or 2048) with ndec = 2^K
 // R = 8: the radix-8 Stockham item (8 bins per lane; 512-lane workgroups at
 // M_bin = 4096, 256 at 2048)
 template <int M, bool RECUR, int K = -1, int R = 16>
@@ -1738,7 +1764,8 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (R == 8 ? 4 : 2)) void dm_b
     unsigned long long *__restrict__ ctr) {
     using Sh = FusedShape<M, R>;
     static_assert(R == 8 || Sh::WG == 256, "radix-16 batched launches use 256-lane workgroups");
-    static_assert(K < 0 || (M == 4096 && R == 16), "the three-pass item is built for M_bin = 4096");
+    static_assert(K < 0 || ((M == 4096 || M == 2048) && R == 16),
+                  "the three-pass item is built for M_bin 4096 and 2048");
     __shared__ cpair sh[K >= 0 ? kX3Lds : Sh::C * Sh::STRIDE];
     __shared__ long long s_item;
     const int q = blockIdx.x % kBatchQueues;
@@ -1766,7 +1793,7 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (R == 8 ? 4 : 2)) void dm_b
         const int dt = (int)(rest % a.ndt);
         const int cg = (int)((rest / a.ndt) * a.inner + ci);
         if constexpr (K >= 0)
-            dm_item_x3<RECUR, K>(a, MemDms{beams[b].dms}, dt, cg, sh);
+            dm_item_x3<RECUR, K, MemDms, false, M>(a, MemDms{beams[b].dms}, dt, cg, sh);
         else
             dm_item<M, R, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
     }
@@ -1833,9 +1860,10 @@ int ensure_twiddles() {
     if (hipMemcpyToSymbol(HIP_SYMBOL(cdmt::g_stage_tw), st.data(),
                           sizeof(float2) * st.size()) != hipSuccess)
         return CDMT_E_DEVICE;
-    // the M_bin = 4096 three-pass schedule: pass 2 [g][k] = exp(+2 pi i g k / 256),
-    // pass 3 [l][r] = exp(+2 pi i r l / 4096)
-    std::vector<float2> t1(16 * 16), t2(256 * 16);
+    // the three-pass schedules: pass 2 [g][k] = exp(+2 pi i g k / 256); pass 3
+    // at M_bin 4096 [l][r] = exp(+2 pi i r l / 4096), at M_bin 2048 [l][r] =
+    // exp(+2 pi i (r & 7)(l + 128 (r >> 3)) / 2048)
+    std::vector<float2> t1(16 * 16), t2(256 * 16), t2h(128 * 16);
     for (int g = 0; g < 16; ++g)
         for (int k = 0; k < 16; ++k) {
             const double ang = 2.0 * M_PI * ((double)((g * k) % 256) / 256.0);
@@ -1846,9 +1874,17 @@ int ensure_twiddles() {
             const double ang = 2.0 * M_PI * ((double)((l * r) % 4096) / 4096.0);
             t2[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
+    for (int l = 0; l < 128; ++l)
+        for (int r = 0; r < 16; ++r) {
+            const int e = ((r & 7) * (l + 128 * (r >> 3))) % 2048;
+            const double ang = 2.0 * M_PI * ((double)e / 2048.0);
+            t2h[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
     if (hipMemcpyToSymbol(HIP_SYMBOL(g_tw1), t1.data(), sizeof(float2) * t1.size()) !=
             hipSuccess ||
         hipMemcpyToSymbol(HIP_SYMBOL(g_tw2), t2.data(), sizeof(float2) * t2.size()) !=
+            hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(g_tw2h), t2h.data(), sizeof(float2) * t2h.size()) !=
             hipSuccess)
         return CDMT_E_DEVICE;
     g_init_done[dev] = 1;
@@ -1925,7 +1961,7 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
 
 
 
-// The M_bin = 4096 three-pass schedule sums ndec = 2^K samples across lanes
+// The three-pass schedules (M_bin 4096, 2048) sum ndec = 2^K samples across lanes
 // aligned to multiples of ndec: K for this launch, or -1 when the plan needs
 // the general kernel (other ndec, n_d / 2 not a multiple of ndec, or the
 // schedule switched off).
@@ -1938,17 +1974,18 @@ int x3_k(const FusedArgs &a) {
     return -1;
 }
 
+template <int M>
 void launch_x3(bool recur, int k, int grid, const FusedArgs &a, const DmList &dl,
               hipStream_t st) {
     switch (k + (recur ? 4 : 0)) {
-    case 0: fused_dedisperse_x3<false, 0><<<grid, 256, 0, st>>>(a, dl); break;
-    case 1: fused_dedisperse_x3<false, 1><<<grid, 256, 0, st>>>(a, dl); break;
-    case 2: fused_dedisperse_x3<false, 2><<<grid, 256, 0, st>>>(a, dl); break;
-    case 3: fused_dedisperse_x3<false, 3><<<grid, 256, 0, st>>>(a, dl); break;
-    case 4: fused_dedisperse_x3<true, 0><<<grid, 256, 0, st>>>(a, dl); break;
-    case 5: fused_dedisperse_x3<true, 1><<<grid, 256, 0, st>>>(a, dl); break;
-    case 6: fused_dedisperse_x3<true, 2><<<grid, 256, 0, st>>>(a, dl); break;
-    default: fused_dedisperse_x3<true, 3><<<grid, 256, 0, st>>>(a, dl); break;
+    case 0: fused_dedisperse_x3<false, 0, M><<<grid, 256, 0, st>>>(a, dl); break;
+    case 1: fused_dedisperse_x3<false, 1, M><<<grid, 256, 0, st>>>(a, dl); break;
+    case 2: fused_dedisperse_x3<false, 2, M><<<grid, 256, 0, st>>>(a, dl); break;
+    case 3: fused_dedisperse_x3<false, 3, M><<<grid, 256, 0, st>>>(a, dl); break;
+    case 4: fused_dedisperse_x3<true, 0, M><<<grid, 256, 0, st>>>(a, dl); break;
+    case 5: fused_dedisperse_x3<true, 1, M><<<grid, 256, 0, st>>>(a, dl); break;
+    case 6: fused_dedisperse_x3<true, 2, M><<<grid, 256, 0, st>>>(a, dl); break;
+    default: fused_dedisperse_x3<true, 3, M><<<grid, 256, 0, st>>>(a, dl); break;
     }
 }
 
@@ -1991,8 +2028,8 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
                     fused_dedisperse_mx<true, BF><<<grid, WG, 0, st>>>(a, dl);
                 else
                     fused_dedisperse_mx<false, BF><<<grid, WG, 0, st>>>(a, dl);
-            } else if (M == 4096 && R == 16 && x3_k(a) >= 0) {
-                launch_x3(recur, x3_k(a), grid, a, dl, st);
+            } else if ((M == 4096 || M == 2048) && R == 16 && x3_k(a) >= 0) {
+                launch_x3<M == 4096 ? 4096 : 2048>(recur, x3_k(a), grid, a, dl, st);
             } else {
                 if (recur)
                     fused_dedisperse<M, R, true><<<grid, WG, 0, st>>>(a, dl);
@@ -2410,13 +2447,13 @@ int batch_upload(cdmt_batch_s *bt) {
         rec[b] = recur ? 1 : 0;
         if (bt->fft_sched[b] >= 0)
             T.a.schedule = bt->fft_sched[b];
-        kk[b] = p->m == 4096 && rr[b] == 16 ? x3_k(T.a) : -1;
+        kk[b] = (p->m == 4096 || p->m == 2048) && rr[b] == 16 ? x3_k(T.a) : -1;
         T.dms = reinterpret_cast<const double *>(bt->ws + bt->dm_off) + dm_at[b];
     }
     for (int m = 64; m <= 4096; m *= 2) {
       for (int r = 1; r >= 0; --r) {
         for (int R = 16; R >= 8; R -= 8) {
-          for (int k = -1; k <= (m == 4096 && R == 16 ? 3 : -1); ++k) {
+          for (int k = -1; k <= ((m == 4096 || m == 2048) && R == 16 ? 3 : -1); ++k) {
             cdmt_batch_s::Launch L{m, r, k, R, (int)tab.size(), 0, 0};
             for (int b = 0; b < nbeam; ++b) {
                 if (bt->beams[b].plan->m != m || rec[b] != r || kk[b] != k || rr[b] != R)
@@ -2465,17 +2502,18 @@ void batch_launch8(int recur, const BatchBeam *tab, int count, long long items,
         dm_batch<M, false, -1, 8><<<grid, WG, 0, st>>>(tab, count, items, ctr);
 }
 
+template <int M>
 void batch_launch_x3(int recur, int k, const BatchBeam *tab, int count, long long items,
                     unsigned long long *ctr, int grid, hipStream_t st) {
     switch (k + (recur ? 4 : 0)) {
-    case 0: dm_batch<4096, false, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    case 1: dm_batch<4096, false, 1><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    case 2: dm_batch<4096, false, 2><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    case 3: dm_batch<4096, false, 3><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    case 4: dm_batch<4096, true, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    case 5: dm_batch<4096, true, 1><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    case 6: dm_batch<4096, true, 2><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
-    default: dm_batch<4096, true, 3><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 0: dm_batch<M, false, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 1: dm_batch<M, false, 1><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 2: dm_batch<M, false, 2><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 3: dm_batch<M, false, 3><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 4: dm_batch<M, true, 0><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 5: dm_batch<M, true, 1><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    case 6: dm_batch<M, true, 2><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
+    default: dm_batch<M, true, 3><<<grid, 256, 0, st>>>(tab, count, items, ctr); break;
     }
 }
 
@@ -2509,7 +2547,10 @@ int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
         unsigned long long *c = ctr + k * kBatchQueues;
         const BatchBeam *t = tab + L.first;
         if (L.k >= 0) {
-            batch_launch_x3(L.recur, L.k, t, L.count, L.items, c, grid, st);
+            if (L.m == 4096)
+                batch_launch_x3<4096>(L.recur, L.k, t, L.count, L.items, c, grid, st);
+            else
+                batch_launch_x3<2048>(L.recur, L.k, t, L.count, L.items, c, grid, st);
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
             continue;
@@ -2763,10 +2804,10 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
     bt->dirty = true;
     // the DM stage's radix schedule, per M_bin (the beams of one M_bin share
     // its launches), each candidate timed on the whole batch with the other
-    // M_bin unchanged: at M_bin = 4096 the three-pass transform (schedule 0,
-    // where the beam allows it), radix-16 and radix-8 Stockham stages
-    // (schedule 1 with 16 or 8 bins per lane); at 2048 radix 16 or 8; other
-    // M_bin have the radix-16 stages only
+    // M_bin unchanged: at M_bin 4096 and 2048 the three-pass transform
+    // (schedule 0, where the beam allows it), radix-16 and radix-8 Stockham
+    // stages (schedule 1 with 16 or 8 bins per lane); other M_bin have the
+    // radix-16 stages only
     for (int m = 2048; m <= 4096 && !r; m *= 2) {
         std::vector<int> beams_m;
         for (int b = 0; b < (int)bt->beams.size(); ++b)
@@ -2778,7 +2819,7 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
         const Cand cands[] = {{0, 16}, {1, 16}, {1, 8}};
         float best_c = 0.f;
         int pick = 0;
-        for (int ci = (m == 4096 ? 0 : 1); ci < 3 && !r; ++ci) {
+        for (int ci = 0; ci < 3 && !r; ++ci) {
             for (int b : beams_m) {
                 bt->fft_sched[b] = cands[ci].sched;
                 bt->lane_bins[b] = cands[ci].bins;

@@ -112,6 +112,9 @@ CASES = [
     (1, 65536, 8192, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 6, 16),   # M = 4096, ndec 4
     (2, 65536, 15360, 16, 8, 2, "ci8", oracle.SUBBAND, -1, 9, 8, 8), # same, 8 bins per lane
     (1, 32768, 4096, 16, 2, 2, "cf32", oracle.CHANNEL, 1, 5, 2, 8),  # M = 2048, 8 bins per lane
+    (2, 32768, 4096, 16, 4, 2, "ci8", oracle.SUBBAND, -1, 6, 4),     # M = 2048, three passes
+    (1, 32768, 4096, 16, 8, 2, "cf32", oracle.CHANNEL, 1, 5, 16),    # same, ndec 8
+    (3, 2048, 512, 1, 2, 3, "cf32", oracle.CHANNEL, -1, 5, 4),       # M = 2048, 9 chunks (odd)
     (1, 131072, 16384, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 3, 1),  # M = 8192, nfft 2^17
     (3, 1024, 256, 8, 2, 3, "ci8", oracle.CHANNEL, -1, 5, 4),        # nfft 2^10, one-pass forward
     (2, 2048, 512, 16, 4, 3, "cf32", oracle.SUBBAND, 1, 6, 3),       # nfft 2^11, M = 128
