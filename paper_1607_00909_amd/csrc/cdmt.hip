@@ -778,6 +778,14 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         const int mlane = Lc & ~((1 << K) - 1);
         float *out = a.out + (long long)d * a.ntime_out * a.nch_out +
                      (long long)b * a.tblk * a.t_stride + col * a.col_stride;
+        // ndec <= 4 (4 to 16 values per lane): stores through a raw buffer
+        // over this block's tblk samples of the column (the launch keeps its
+        // byte extent under 2^31), a discarded sample at an offset past it,
+        // which the range check drops: 32-bit offsets instead of 64-bit
+        // addresses keep these forms from spilling.  ndec = 8 keeps plain
+        // stores (measured 1% faster there).
+        const __amdgpu_buffer_rsrc_t oview = __builtin_amdgcn_make_buffer_rsrc(
+            out, (short)0, valid ? a.tblk * a.t_stride * 4 : 0, 0x00020000);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
             int q;
@@ -787,8 +795,14 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             else q = 8 * r + 4 * ((L >> 1) & 1) + 2 * (L & 1) + ((L >> 2) & 1);
             const int m = mlane + (M == 4096 ? 256 * q : LC * (q >> 3) + 256 * (q & 7));
             const int tq = (m - a.nd_half) >> K;
-            if (valid && m >= a.nd_half && tq < a.tblk)
-                out[(long long)tq * a.t_stride] = o[r];
+            const bool keep = m >= a.nd_half && tq < a.tblk;
+            if constexpr (K <= 2) {
+                __builtin_amdgcn_raw_buffer_store_b32(
+                    __float_as_uint(o[r]), oview, keep ? tq * a.t_stride * 4 : (int)0x80000000, 0, 0);
+            } else {
+                if (valid && keep)
+                    out[(long long)tq * a.t_stride] = o[r];
+            }
         }
     };
     if constexpr (RECUR) {
@@ -1963,10 +1977,10 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
 
 // The three-pass schedules (M_bin 4096, 2048) sum ndec = 2^K samples across lanes
 // aligned to multiples of ndec: K for this launch, or -1 when the plan needs
-// the general kernel (other ndec, n_d / 2 not a multiple of ndec, or the
-// schedule switched off).
+// the general kernel (other ndec, n_d / 2 not a multiple of ndec, a block's
+// column spanning 2^31 bytes or more, or the schedule switched off).
 int x3_k(const FusedArgs &a) {
-    if (a.schedule != 0)
+    if (a.schedule != 0 || 4LL * a.tblk * a.t_stride >= 0x80000000LL)
         return -1;
     for (int k = 0; k <= 3; ++k)
         if (a.ndec == (1 << k))
