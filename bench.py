@@ -74,14 +74,14 @@ def mx_mfma_flops_per_chunk_dm() -> float:
 
 def dm_stage_kernel(w, recurrence: bool) -> str:
     """Name of the FP32 DM-stage kernel the library launches for workload w
-    (default schedule, 16 bins per lane): the three-pass kernel at M_bin 4096
-    or 2048 when ndec = 2^K (K <= 3) divides n_d / 2, else the radix-16
+    (default schedule, 16 bins per lane): the three-pass kernel at M_bin 4096,
+    2048 or 1024 when ndec = 2^K (K <= 3) divides n_d / 2, else the radix-16
     Stockham kernel."""
     import math
     nd_half = w.noverlap // w.nchan // 2
     k = int(math.log2(w.ndec)) if w.ndec & (w.ndec - 1) == 0 else -1
     r = "true" if recurrence else "false"
-    if w.m in (2048, 4096) and 0 <= k <= 3 and nd_half % w.ndec == 0:
+    if w.m in (1024, 2048, 4096) and 0 <= k <= 3 and nd_half % w.ndec == 0:
         return f"fused_dedisperse_x3<{r}, {k}, {w.m}>"
     return f"fused_dedisperse<{w.m}, 16, {r}>"
 
@@ -152,7 +152,7 @@ def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
     channels, overlap, DM list and output, in one persistent DM-stage launch
     per M_bin (1024, 2048 and 4096 here), replayed as a hipGraph after the
     autotuner picked each beam's forward-FFT split, the DM-stage schedule of
-    the M_bin 2048 and 4096 beams, the DM tile and the grid."""
+    the M_bin 1024, 2048 and 4096 beams, the DM tile and the grid."""
     import math
     draws = synth.batch_draws()
     beams, dm_seconds = [], 0.0
@@ -197,7 +197,7 @@ def batch_leg(cdmt, synth, torch, dev, steps: int, reps: int):
            # the DM-stage radix schedule the autotuner kept per M_bin: "x3"
            # three radix-16 passes, "s16" / "s8" radix-16 / radix-8 Stockham
            "dm_stage_radix": {str(m): sorted({
-               "x3" if batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_FFT_SCHEDULE) == 0 and m >= 2048
+               "x3" if batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_FFT_SCHEDULE) == 0 and m >= 1024
                and batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_LANE_BINS) == 16
                else "s%d" % (8 if batch.beam_get(i, cdmt.CDMT_BATCH_BEAM_LANE_BINS) == 8
                              and m >= 2048 else 16)

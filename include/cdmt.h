@@ -75,12 +75,12 @@ enum cdmt_opt {
                                 circular convolution would reach the kept samples,
                                 Sec. 2); 0: no such check (a deliberately short overlap) */
     CDMT_OPT_FFT_SCHEDULE = 10 /* performance knob of the FP32 DM stage: 0 (default):
-                                at M_bin 4096 or 2048 with ndec in {1, 2, 4, 8}
-                                dividing n_d / 2, the backward FFT runs as three
-                                passes (radix 16, 16, 16 or 16, 16, 8) with two
-                                LDS exchanges per DM (the first within each wave)
-                                and detection and downsampling in registers;
-                                other plans as 1.
+                                at M_bin 4096, 2048 or 1024 with ndec in
+                                {1, 2, 4, 8} dividing n_d / 2, the backward FFT
+                                runs as three passes (radix 16, 16 and M_bin /
+                                256) with two LDS exchanges per DM (the first
+                                within each wave; at 1024 both) and detection and
+                                downsampling in registers; other plans as 1.
                                 1: radix-16 Stockham stages with every digit
                                 exchange and the detected power through LDS (all
                                 M_bin).  Same results up to FP32 rounding      */

@@ -500,6 +500,8 @@ __device__ __align__(16) float2 g_tw1[16 * 16];
 __device__ __align__(16) float2 g_tw2[256 * 16];
 // M_bin = 2048 pass 3: row l (0..127), column r: exp(+2 pi i (r & 7)(l + 128 (r >> 3)) / 2048)
 __device__ __align__(16) float2 g_tw2h[128 * 16];
+// M_bin = 1024 pass 3: row l (0..63), column r: exp(+2 pi i (r & 3)(l + 64 (r >> 2)) / 1024)
+__device__ __align__(16) float2 g_tw2q[64 * 16];
 
 constexpr int kX3Region = 4 * 16 * 17;       // bin pairs of LDS per wave
 constexpr int kX3Lds = 4 * kX3Region;        // per workgroup (68 KiB)
@@ -552,10 +554,13 @@ __device__ __forceinline__ void wave_lds_fence() {
 // (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
 template <bool RECUR, int K, class DMS, bool TWL = false, int M = 4096>
 __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
-    static_assert(M == 4096 || M == 2048, "three-pass schedules: 16 x 16 x 16 and 16 x 16 x 8");
+    static_assert(M == 4096 || M == 2048 || M == 1024,
+                  "three-pass schedules: radix 16 x 16 x P3, P3 = M / 256 = 16, 8 or 4");
     // M = 4096: one chunk per workgroup; M = 2048: two, chunk f on waves
-    // 2f, 2f + 1 (a second chunk past the end runs on zeros, stores nothing)
+    // 2f, 2f + 1; M = 1024: four, one per wave (a chunk past the end runs on
+    // zeros and stores nothing)
     constexpr int LC = M / 16;            // lanes per chunk
+    constexpr int P3 = M / 256;           // radix of pass 3
     const int L = threadIdx.x;
     // the chunk index is uniform over a wave: kept scalar (readfirstlane)
     const int f = M == 4096 ? 0 : __builtin_amdgcn_readfirstlane(L / LC);
@@ -613,7 +618,8 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
     // pass 3's twiddles (DM-invariant): row Lc of the M_bin's table
     float2 tw2[16];
     {
-        const float4 *row = reinterpret_cast<const float4 *>((M == 4096 ? g_tw2 : g_tw2h) + 16 * Lc);
+        const float2 *tab = M == 4096 ? g_tw2 : M == 2048 ? g_tw2h : g_tw2q;
+        const float4 *row = reinterpret_cast<const float4 *>(tab + 16 * Lc);
 #pragma unroll
         for (int h = 0; h < 8; ++h) {
             const float4 x = row[h];
@@ -635,18 +641,24 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
 
     // LDS: exchange 1 writes at xw + 17 k (row k of 17 slots, column l03 of
     // block (w, l45)) and reads at x1r + r (row l03, column r); exchange 2
-    // writes at xw + 16 k (rows of 16) and reads at x2r + x2off(r): at
-    // M = 4096 block G0 = r of the workgroup's regions, row L >> 4 = K1,
-    // column l03 = K0; at M = 2048 block G0 = r & 7 of the chunk's two
-    // regions, row (Lc >> 4) + 8 (r >> 3) = K1.  The block pitch (272 = 16
-    // mod 64 slots) and the row pitches keep all 64 lanes of a wave on
-    // distinct 16-byte slots mod 64 in every access.
+    // writes at xw + 16 k (rows of 16) and reads at x2r + x2off(r): block
+    // G0 = r mod P3 of the chunk's regions, row K1 = (Lc >> 4) + (LC / 16)
+    // (r / P3), column K0 = l03 (at M = 4096: block r of the workgroup's
+    // regions, row L >> 4).  The block pitch (272 = 16 mod 64 slots) and the
+    // row pitches keep all 64 lanes of a wave on distinct 16-byte slots mod
+    // 64 in every access.  At M = 1024 a chunk's exchanges stay within its
+    // wave, so a wave-level fence replaces the workgroup barriers.
     cpair *const xw = sh + w * kX3Region + 272 * l45 + l03;
     const cpair *const x1r = sh + w * kX3Region + 272 * l45 + 17 * l03;
     const cpair *const x2r = sh + (LC / 64) * f * kX3Region + Lc;
     auto x2off = [](int r) {
-        return M == 4096 ? kX3Region * (r >> 2) + 272 * (r & 3)
-                         : kX3Region * ((r >> 2) & 1) + 272 * (r & 3) + 128 * (r >> 3);
+        return kX3Region * ((r % P3) >> 2) + 272 * (r & 3) + LC * (r / P3);
+    };
+    auto xbarrier = []() {
+        if constexpr (M == 1024)
+            wave_lds_fence();
+        else
+            __syncthreads();
     };
 
     // output: this lane's samples after the sum over lane bits 0..K-1; column
@@ -706,7 +718,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         for (int k = 1; k < 16; ++k)
             v[k] = cdmt::pmul(v[k], tw1[k]);
         // exchange 1 (within the wave)
-        __syncthreads();
+        xbarrier();
 #pragma unroll
         for (int k = 0; k < 16; ++k)
             xw[17 * k] = v[k];
@@ -721,7 +733,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
 #pragma unroll
         for (int k = 0; k < 16; ++k)
             xw[16 * k] = v[k];
-        __syncthreads();
+        xbarrier();
         // from exchange 2's reads to the stores this wave goes before the
         // CU's other waves of normal priority (measured 1% faster than
         // leaving the order to the arbiter)
@@ -729,20 +741,17 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             v[r] = x2r[x2off(r)];
-        // pass 3 (at M = 2048 two DFT-8 over registers r & 7, r >> 3 fixed;
-        // tw2 is 1 at r = 0 and, for M = 2048, at r = 8)
+        // pass 3: 16 / P3 DFTs of P3 points over registers r mod P3 (r / P3
+        // fixed); tw2 is 1 where r mod P3 = 0
 #pragma unroll
         for (int r = 1; r < 16; ++r)
-            if (M == 4096 || r != 8)
+            if (r % P3 != 0)
                 v[r] = cdmt::pmul(v[r], tw2[r]);
-        if constexpr (M == 4096) {
-            cdmt::dft16<+1>(v);
-        } else {
-            cdmt::dft8<+1>(v);
-            cdmt::dft8<+1>(v + 8);
-        }
+#pragma unroll
+        for (int h = 0; h < 16; h += P3)
+            cdmt::dft<P3, +1>(v + h);
 
-        // detection: register q holds sample Lc + LC (q >> 3) + 256 (q & 7)
+        // detection: register q holds sample Lc + LC (q / P3) + 256 (q mod P3)
         // (at M = 4096: Lc + 256 q)
         float p[16];
 #pragma unroll
@@ -793,7 +802,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             else if constexpr (K == 1) q = 2 * r + (L & 1);
             else if constexpr (K == 2) q = 4 * r + 2 * ((L >> 1) & 1) + (L & 1);
             else q = 8 * r + 4 * ((L >> 1) & 1) + 2 * (L & 1) + ((L >> 2) & 1);
-            const int m = mlane + (M == 4096 ? 256 * q : LC * (q >> 3) + 256 * (q & 7));
+            const int m = mlane + LC * (q / P3) + 256 * (q % P3);
             const int tq = (m - a.nd_half) >> K;
             const bool keep = m >= a.nd_half && tq < a.tblk;
             if constexpr (K <= 2) {
@@ -1769,7 +1778,7 @@ __global__ void batch_reset(unsigned long long *ctr, int n) {
         ctr[i] = 0;
 }
 
-// K >= 0: the three-pass item (dm_item_x3, M_bin 4096 or 2048) with ndec = 2^K
+// K >= 0: the three-pass item (dm_item_x3, M_bin 4096, 2048 or 1024) with ndec = 2^K
 // R = 8: the radix-8 Stockham item (8 bins per lane; 512-lane workgroups at
 // M_bin = 4096, 256 at 2048)
 template <int M, bool RECUR, int K = -1, int R = 16>
@@ -1778,8 +1787,8 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (R == 8 ? 4 : 2)) void dm_b
     unsigned long long *__restrict__ ctr) {
     using Sh = FusedShape<M, R>;
     static_assert(R == 8 || Sh::WG == 256, "radix-16 batched launches use 256-lane workgroups");
-    static_assert(K < 0 || ((M == 4096 || M == 2048) && R == 16),
-                  "the three-pass item is built for M_bin 4096 and 2048");
+    static_assert(K < 0 || ((M == 4096 || M == 2048 || M == 1024) && R == 16),
+                  "the three-pass item is built for M_bin 4096, 2048 and 1024");
     __shared__ cpair sh[K >= 0 ? kX3Lds : Sh::C * Sh::STRIDE];
     __shared__ long long s_item;
     const int q = blockIdx.x % kBatchQueues;
@@ -1876,8 +1885,10 @@ int ensure_twiddles() {
         return CDMT_E_DEVICE;
     // the three-pass schedules: pass 2 [g][k] = exp(+2 pi i g k / 256); pass 3
     // at M_bin 4096 [l][r] = exp(+2 pi i r l / 4096), at M_bin 2048 [l][r] =
-    // exp(+2 pi i (r & 7)(l + 128 (r >> 3)) / 2048)
-    std::vector<float2> t1(16 * 16), t2(256 * 16), t2h(128 * 16);
+    // exp(+2 pi i (r & 7)(l + 128 (r >> 3)) / 2048), at M_bin 1024 [l][r] =
+    // exp(+2 pi i (r & 3)(l + 64 (r >> 2)) / 1024), at M_bin 1024 [l][r] =
+    // exp(+2 pi i (r & 3)(l + 64 (r >> 2)) / 1024)
+    std::vector<float2> t1(16 * 16), t2(256 * 16), t2h(128 * 16), t2q(64 * 16);
     for (int g = 0; g < 16; ++g)
         for (int k = 0; k < 16; ++k) {
             const double ang = 2.0 * M_PI * ((double)((g * k) % 256) / 256.0);
@@ -1894,11 +1905,19 @@ int ensure_twiddles() {
             const double ang = 2.0 * M_PI * ((double)e / 2048.0);
             t2h[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
         }
+    for (int l = 0; l < 64; ++l)
+        for (int r = 0; r < 16; ++r) {
+            const int e = ((r & 3) * (l + 64 * (r >> 2))) % 1024;
+            const double ang = 2.0 * M_PI * ((double)e / 1024.0);
+            t2q[16 * l + r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+        }
     if (hipMemcpyToSymbol(HIP_SYMBOL(g_tw1), t1.data(), sizeof(float2) * t1.size()) !=
             hipSuccess ||
         hipMemcpyToSymbol(HIP_SYMBOL(g_tw2), t2.data(), sizeof(float2) * t2.size()) !=
             hipSuccess ||
         hipMemcpyToSymbol(HIP_SYMBOL(g_tw2h), t2h.data(), sizeof(float2) * t2h.size()) !=
+            hipSuccess ||
+        hipMemcpyToSymbol(HIP_SYMBOL(g_tw2q), t2q.data(), sizeof(float2) * t2q.size()) !=
             hipSuccess)
         return CDMT_E_DEVICE;
     g_init_done[dev] = 1;
@@ -1975,7 +1994,7 @@ int launch_forward(const cdmt_plan_s *p, void *ws, const void *x, int nblock, hi
 
 
 
-// The three-pass schedules (M_bin 4096, 2048) sum ndec = 2^K samples across lanes
+// The three-pass schedules (M_bin 4096, 2048, 1024) sum ndec = 2^K samples across lanes
 // aligned to multiples of ndec: K for this launch, or -1 when the plan needs
 // the general kernel (other ndec, n_d / 2 not a multiple of ndec, a block's
 // column spanning 2^31 bytes or more, or the schedule switched off).
@@ -2042,8 +2061,8 @@ int launch_fused_m(const FusedArgs &a0, const double *dms, int ndm, hipStream_t 
                     fused_dedisperse_mx<true, BF><<<grid, WG, 0, st>>>(a, dl);
                 else
                     fused_dedisperse_mx<false, BF><<<grid, WG, 0, st>>>(a, dl);
-            } else if ((M == 4096 || M == 2048) && R == 16 && x3_k(a) >= 0) {
-                launch_x3<M == 4096 ? 4096 : 2048>(recur, x3_k(a), grid, a, dl, st);
+            } else if ((M == 4096 || M == 2048 || M == 1024) && R == 16 && x3_k(a) >= 0) {
+                launch_x3<(M == 4096 || M == 2048 ? M : 1024)>(recur, x3_k(a), grid, a, dl, st);
             } else {
                 if (recur)
                     fused_dedisperse<M, R, true><<<grid, WG, 0, st>>>(a, dl);
@@ -2461,13 +2480,13 @@ int batch_upload(cdmt_batch_s *bt) {
         rec[b] = recur ? 1 : 0;
         if (bt->fft_sched[b] >= 0)
             T.a.schedule = bt->fft_sched[b];
-        kk[b] = (p->m == 4096 || p->m == 2048) && rr[b] == 16 ? x3_k(T.a) : -1;
+        kk[b] = p->m >= 1024 && rr[b] == 16 ? x3_k(T.a) : -1;
         T.dms = reinterpret_cast<const double *>(bt->ws + bt->dm_off) + dm_at[b];
     }
     for (int m = 64; m <= 4096; m *= 2) {
       for (int r = 1; r >= 0; --r) {
         for (int R = 16; R >= 8; R -= 8) {
-          for (int k = -1; k <= ((m == 4096 || m == 2048) && R == 16 ? 3 : -1); ++k) {
+          for (int k = -1; k <= (m >= 1024 && R == 16 ? 3 : -1); ++k) {
             cdmt_batch_s::Launch L{m, r, k, R, (int)tab.size(), 0, 0};
             for (int b = 0; b < nbeam; ++b) {
                 if (bt->beams[b].plan->m != m || rec[b] != r || kk[b] != k || rr[b] != R)
@@ -2563,8 +2582,10 @@ int batch_enqueue(cdmt_batch_s *bt, hipStream_t st) {
         if (L.k >= 0) {
             if (L.m == 4096)
                 batch_launch_x3<4096>(L.recur, L.k, t, L.count, L.items, c, grid, st);
-            else
+            else if (L.m == 2048)
                 batch_launch_x3<2048>(L.recur, L.k, t, L.count, L.items, c, grid, st);
+            else
+                batch_launch_x3<1024>(L.recur, L.k, t, L.count, L.items, c, grid, st);
             if (hipGetLastError() != hipSuccess)
                 return CDMT_E_DEVICE;
             continue;
@@ -2820,9 +2841,9 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
     // its launches), each candidate timed on the whole batch with the other
     // M_bin unchanged: at M_bin 4096 and 2048 the three-pass transform
     // (schedule 0, where the beam allows it), radix-16 and radix-8 Stockham
-    // stages (schedule 1 with 16 or 8 bins per lane); other M_bin have the
-    // radix-16 stages only
-    for (int m = 2048; m <= 4096 && !r; m *= 2) {
+    // stages (schedule 1 with 16 or 8 bins per lane); at 1024 the three-pass
+    // transform and radix-16 stages; other M_bin have the radix-16 stages only
+    for (int m = 1024; m <= 4096 && !r; m *= 2) {
         std::vector<int> beams_m;
         for (int b = 0; b < (int)bt->beams.size(); ++b)
             if (bt->beams[b].plan->m == m)
@@ -2833,7 +2854,7 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
         const Cand cands[] = {{0, 16}, {1, 16}, {1, 8}};
         float best_c = 0.f;
         int pick = 0;
-        for (int ci = 0; ci < 3 && !r; ++ci) {
+        for (int ci = 0; ci < (m == 1024 ? 2 : 3) && !r; ++ci) {
             for (int b : beams_m) {
                 bt->fft_sched[b] = cands[ci].sched;
                 bt->lane_bins[b] = cands[ci].bins;

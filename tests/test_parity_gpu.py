@@ -115,6 +115,8 @@ CASES = [
     (2, 32768, 4096, 16, 4, 2, "ci8", oracle.SUBBAND, -1, 6, 4),     # M = 2048, three passes
     (1, 32768, 4096, 16, 8, 2, "cf32", oracle.CHANNEL, 1, 5, 16),    # same, ndec 8
     (3, 2048, 512, 1, 2, 3, "cf32", oracle.CHANNEL, -1, 5, 4),       # M = 2048, 9 chunks (odd)
+    (2, 16384, 2048, 16, 2, 2, "cf32", oracle.SUBBAND, 1, 5, 16),    # M = 1024, three passes
+    (3, 1024, 256, 1, 8, 3, "ci8", oracle.CHANNEL, -1, 5, 4),        # M = 1024, 9 chunks
     (1, 131072, 16384, 16, 4, 2, "cf32", oracle.CHANNEL, -1, 3, 1),  # M = 8192, nfft 2^17
     (3, 1024, 256, 8, 2, 3, "ci8", oracle.CHANNEL, -1, 5, 4),        # nfft 2^10, one-pass forward
     (2, 2048, 512, 16, 4, 3, "cf32", oracle.SUBBAND, 1, 6, 3),       # nfft 2^11, M = 128
