@@ -552,7 +552,7 @@ __device__ __forceinline__ void wave_lds_fence() {
 
 // One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
 // (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
-template <bool RECUR, int K, class DMS, bool TWL = false, int M = 4096>
+template <bool RECUR, int K, class DMS, int TWL = 0, int M = 4096>
 __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
     static_assert(M == 4096 || M == 2048 || M == 1024,
                   "three-pass schedules: radix 16 x 16 x P3, P3 = M / 256 = 16, 8 or 4");
@@ -627,13 +627,16 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             tw2[2 * h + 1] = make_float2(x.z, x.w);
         }
     }
-    // pass 2's twiddle row G1, columns 2h, 2h + 1 at row1[TWS h]: from L1, or
-    // (TWL: sh holds kX3TwLds more bin pairs) from the LDS copies
+    // pass 2's twiddle row G1, columns 2h, 2h + 1 at row1[TWS h]: from L1
+    // (TWL = 0), or from the LDS copies after sh's kX3Lds bin pairs, written
+    // here (TWL = 1) or by the caller before a barrier (TWL = 2)
     const float4 *row1;
-    constexpr int TWS = TWL ? 16 : 1;
-    if constexpr (TWL) {
-        put_tw1_lds(reinterpret_cast<float2 *>(sh + kX3Lds));
-        __syncthreads();
+    constexpr int TWS = TWL != 0 ? 16 : 1;
+    if constexpr (TWL != 0) {
+        if constexpr (TWL == 1) {
+            put_tw1_lds(reinterpret_cast<float2 *>(sh + kX3Lds));
+            __syncthreads();
+        }
         row1 = reinterpret_cast<const float4 *>(sh + kX3Lds) + 144 * l45 + l03;
     } else {
         row1 = reinterpret_cast<const float4 *>(g_tw1 + 16 * l03);
@@ -837,7 +840,7 @@ __global__ __launch_bounds__(256, 2) void fused_dedisperse_x3(FusedArgs a, DmLis
     const int cg = a.cg0 + (rest / a.ndt) * a.inner + ci;
     // the LDS twiddle table at ndec = 8 (measured 2.3% faster there; at
     // smaller ndec its registers would spill)
-    dm_item_x3<RECUR, K, ArgDms, K == 3, M>(a, ArgDms{dl}, dt, cg, sh);
+    dm_item_x3<RECUR, K, ArgDms, K == 3 ? 1 : 0, M>(a, ArgDms{dl}, dt, cg, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1789,7 +1792,11 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (R == 8 ? 4 : 2)) void dm_b
     static_assert(R == 8 || Sh::WG == 256, "radix-16 batched launches use 256-lane workgroups");
     static_assert(K < 0 || ((M == 4096 || M == 2048 || M == 1024) && R == 16),
                   "the three-pass item is built for M_bin 4096, 2048 and 1024");
-    __shared__ cpair sh[K >= 0 ? kX3Lds : Sh::C * Sh::STRIDE];
+    __shared__ cpair sh[K >= 0 ? kX3Lds + kX3TwLds : Sh::C * Sh::STRIDE];
+    // the three-pass item at ndec = 8 reads pass 2's twiddles from LDS copies
+    // written once here (first read after the loop's first barrier)
+    if constexpr (K == 3)
+        put_tw1_lds(reinterpret_cast<float2 *>(sh + kX3Lds));
     __shared__ long long s_item;
     const int q = blockIdx.x % kBatchQueues;
     const long long lo = total * q / kBatchQueues;
@@ -1816,7 +1823,7 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (R == 8 ? 4 : 2)) void dm_b
         const int dt = (int)(rest % a.ndt);
         const int cg = (int)((rest / a.ndt) * a.inner + ci);
         if constexpr (K >= 0)
-            dm_item_x3<RECUR, K, MemDms, false, M>(a, MemDms{beams[b].dms}, dt, cg, sh);
+            dm_item_x3<RECUR, K, MemDms, K == 3 ? 2 : 0, M>(a, MemDms{beams[b].dms}, dt, cg, sh);
         else
             dm_item<M, R, RECUR>(a, MemDms{beams[b].dms}, dt, cg, sh);
     }
