@@ -49,7 +49,7 @@ enum cdmt_opt {
                                 matrix cores with hi/lo split operands and FP32
                                 accumulation (M_bin = 4096 only, else
                                 CDMT_E_UNSUPPORTED)                                     */
-    CDMT_OPT_DM_TILE = 4,    /* DM trials per workgroup pass, 1..16 (default 16)        */
+    CDMT_OPT_DM_TILE = 4,    /* DM trials per workgroup pass, 1..64 (default 64)        */
     CDMT_OPT_CHIRP_EXACT = 5,/* 1: evaluate the transfer function afresh for every DM;
                                 0 (default): when the DM list is an arithmetic
                                 progression, advance it by one complex factor per DM
@@ -308,7 +308,7 @@ typedef struct {
 } cdmt_beam_t;
 
 enum cdmt_batch_opt {
-    CDMT_BATCH_DM_TILE = 0,    /* DM trials per item for every beam, 1..16; 0 = each plan's */
+    CDMT_BATCH_DM_TILE = 0,    /* DM trials per item for every beam, 1..64; 0 = each plan's */
     CDMT_BATCH_WG_PER_CU = 1,  /* persistent workgroups per compute unit, 1..8 (default 2)  */
     CDMT_BATCH_ITEMS = 2,      /* (get only) work items of the DM stage                      */
     CDMT_BATCH_LAUNCHES = 3    /* (get only) persistent launches (one per distinct M_bin)    */
@@ -366,10 +366,10 @@ int cdmt_batch_run_graph(cdmt_batch_t batch, void *hip_stream);
  * beam's N_bin is timed on that beam's forward stage alone and the fastest
  * kept (CDMT_BATCH_BEAM_FWD_N2).  Then the DM stage's radix schedule per
  * M_bin (beams of one M_bin share launches), each candidate timed on the
- * whole batch: at M_bin = 4096 the three-pass transform, radix-16 and radix-8
- * Stockham stages; at 2048 radix 16 and 8 (CDMT_BATCH_BEAM_FFT_SCHEDULE,
- * CDMT_BATCH_BEAM_LANE_BINS).  Then the
- * whole batch for every DM tile in {4, 8, 16} and 2 or 4 workgroups per CU;
+ * whole batch: at M_bin 4096 and 2048 the three-pass transform, radix-16 and
+ * radix-8 Stockham stages; at 1024 the three-pass transform and radix 16
+ * (CDMT_BATCH_BEAM_FFT_SCHEDULE, CDMT_BATCH_BEAM_LANE_BINS).  Then the
+ * whole batch for every DM tile in {8, 16, 32, 64} and 2 or 4 workgroups per CU;
  * the fastest setting is kept and its time per run returned in *best_ms
  * (may be NULL).  reps runs per candidate after one warm-up.  Writes the
  * beams' outputs. */

@@ -2686,7 +2686,7 @@ int cdmt_batch_set(cdmt_batch_t bt, int opt, int value) {
         return CDMT_E_ARG;
     switch (opt) {
     case CDMT_BATCH_DM_TILE:
-        if (value < 0 || value > 16)
+        if (value < 0 || value > 64)
             return CDMT_E_ARG;
         // the table is rewritten in place: no run of the batch may be in flight
         if (hipDeviceSynchronize() != hipSuccess)
@@ -2883,7 +2883,7 @@ int cdmt_batch_autotune(cdmt_batch_t bt, void *hip_stream, int reps, float *best
             r = batch_upload(bt);
         }
     }
-    static const int kTiles[] = {4, 8, 16};
+    static const int kTiles[] = {8, 16, 32, 64};
     static const int kWg[] = {2, 4};
     float best = 0.f;
     int bt_tile = 16, bt_wg = 2;

@@ -174,7 +174,7 @@ int cdmt_plan_set(cdmt_plan_t p, int opt, int value) {
         p->precision = value;
         return CDMT_OK;
     case CDMT_OPT_DM_TILE:
-        if (value < 1 || value > 16)
+        if (value < 1 || value > 64)
             return CDMT_E_ARG;
         p->dm_tile = value;
         return CDMT_OK;

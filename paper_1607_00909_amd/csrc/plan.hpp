@@ -11,7 +11,7 @@
 struct cdmt_plan_s {
     int nsub, nfft, noverlap, nchan, ndec;
     double f_centre, bw;
-    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 16, chirp_exact = 0, lane_bins = 16;
+    int input_kind = 0, chirp_ref = 0, sign = -1, precision = 0, dm_tile = 64, chirp_exact = 0, lane_bins = 16;
     int out_layout = 0;     // 0: filterbanks [DM][t][ch], 1: [DM][ch][t]
     int dm_check = 1;       // 1: reject DMs whose Eq. 2 sweep exceeds the overlap
     int fft_schedule = 0;   // DM-stage transform schedule (CDMT_OPT_FFT_SCHEDULE)

@@ -108,7 +108,7 @@ def test_options(lib):
         for opt, val, want in ((cdmt.CDMT_OPT_SIGN, 0, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_INPUT, 2, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_DM_TILE, 0, cdmt.CDMT_E_ARG),
-                               (cdmt.CDMT_OPT_DM_TILE, 17, cdmt.CDMT_E_ARG),
+                               (cdmt.CDMT_OPT_DM_TILE, 65, cdmt.CDMT_E_ARG),
                                (cdmt.CDMT_OPT_PRECISION, 1, cdmt.CDMT_E_UNSUPPORTED),
                                (99, 0, cdmt.CDMT_E_ARG)):
             assert lib.cdmt_plan_set(p, opt, val) == want

@@ -100,7 +100,7 @@ def test_batch_matches_single_beams_and_oracle(hip_lib):
     torch.cuda.synchronize()
     for i, (sp, (plan, nblock, x, dms, out)) in enumerate(zip(SPECS, beams)):
         assert bool(torch.isfinite(out).all()), f"beam {i}: output not fully written"
-        ref = _single(hip_lib, sp, x, 16)
+        ref = _single(hip_lib, sp, x, hip_lib.cdmt_plan_get(plan.handle, hip_lib.CDMT_OPT_DM_TILE))
         torch.cuda.synchronize()
         assert torch.equal(out, ref), f"beam {i} differs from its single-beam run"
         _, v = host[i]
