@@ -1423,7 +1423,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad(FusedArgs a, DmList dl,
 // depend on the DM); the transfer function is evaluated twice per DM, for the
 // forward transform and for the final product, which costs less than
 // re-reading the spectrum from L2 each DM.
-constexpr int kGradTile = 16;
+constexpr int kGradTile = 64;
 
 template <int TILE>
 __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
