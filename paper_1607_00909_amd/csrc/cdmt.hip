@@ -483,15 +483,20 @@ __global__ __launch_bounds__((FusedShape<M, R>::WG), (FusedShape<M, R>::MIN_WAVE
 // adds the two polarisations' power in registers; downsampling by ndec = 2^K
 // sums over m's lowest K bits, lane bits, across lanes (DPP).
 //
-// LDS: each wave owns a region of 4 blocks (one per l45) of 16 rows of 17
-// slots (one slot = one bin pair; the padding column keeps the column reads
-// of 16 consecutive lanes on 16 distinct 16-byte bank groups).  Exchange 1
-// writes element (G1, K0) of block (w, l45) at row K0, column G1 and reads it
-// back within the wave; exchange 2 writes element (G0, K0, K1) into the same
-// region (block G0 & 3 of wave G0 >> 2, row K1, column K0), which no other
-// wave touched since the previous barrier, so each DM needs two barriers: one
-// before exchange 1's writes (every wave has read the previous DM's exchange
-// 2) and one between exchange 2's writes and reads.
+// LDS: each wave owns a region of 4 blocks (one per l45) of 272 slots (one
+// slot = one bin pair).  Exchange 1 writes element (G1, K0) of block (w, l45)
+// at row K0, column G1 of rows of 17 slots and reads it back within the wave;
+// exchange 2 writes element (G0, K0, K1) into the same region (block G0 & 3
+// of wave G0 >> 2, row K1, column K0, rows of 16), which no other wave touched
+// since the previous barrier, so each DM needs two barriers: one before
+// exchange 1's writes (every wave has read the previous DM's exchange 2) and
+// one between exchange 2's writes and reads.
+//
+// The same item serves M_bin 2048 and 1024 with a radix-P3 last pass, P3 =
+// M / 256 (16 x 16 x 8 and 16 x 16 x 4): a chunk then spans M / 1024 waves
+// (two, or one with no workgroup barrier), bins G0 + (M / 256) G1 + (M / 16)
+// G2 with G0 = l45 + 4 (w mod M / 1024), and register r ends with sample
+// Lc + (M / 16)(r / P3) + 256 (r mod P3), Lc the lane within the chunk.
 
 // exp(+2 pi i g k / 256) at [g][k] (pass 2's twiddles, g = G1, k = K0) and
 // exp(+2 pi i r l / 4096) at [l][r] (pass 3's, r = G0, l = K0 + 16 K1, the
@@ -550,8 +555,9 @@ __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// One work item: channel chunk cg, DM tile dt, at M_bin = 4096, ndec = 2^K
-// (K <= 3) and n_d / 2 a multiple of ndec.  sh holds kX3Lds bin pairs.
+// One work item: chunk group cg (4096 / M channel chunks) and DM tile dt, at
+// M_bin = M (4096, 2048 or 1024), ndec = 2^K (K <= 3) and n_d / 2 a multiple
+// of ndec.  sh holds kX3Lds bin pairs (plus kX3TwLds when TWL != 0).
 template <bool RECUR, int K, class DMS, int TWL = 0, int M = 4096>
 __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, int cg, cpair *sh) {
     static_assert(M == 4096 || M == 2048 || M == 1024,
@@ -1772,9 +1778,10 @@ struct BatchBeam {
 
 constexpr int kBatchQueues = 8;
 // launch groups: 7 M_bin x 2 transfer-function forms, plus the three-pass
-// item's 4 downsampling factors x 2 forms at M_bin = 4096, plus the radix-8
-// item (8 bins per lane) x 2 forms at M_bin = 2048 and 4096
-constexpr int kBatchGroups = 26;
+// item's 4 downsampling factors x 2 forms at M_bin 1024, 2048 and 4096, plus
+// the radix-8 item (8 bins per lane) x 2 forms at M_bin 2048 and 4096; each
+// group has kBatchQueues counters in the batch workspace
+constexpr int kBatchGroups = 7 * 2 + 3 * 4 * 2 + 2 * 2;
 
 __global__ void batch_reset(unsigned long long *ctr, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -2506,6 +2513,8 @@ int batch_upload(cdmt_batch_s *bt) {
                 ++L.count;
             }
             if (L.count) {
+                if ((int)bt->launches.size() == kBatchGroups)
+                    return CDMT_E_UNSUPPORTED;   // no counters left (not reached: see kBatchGroups)
                 bt->launches.push_back(L);
                 bt->total += L.items;
             }
