@@ -293,3 +293,32 @@ def test_batch_24_beam_workload(hip_lib):
         torch.cuda.synchronize()
         assert torch.equal(ref, beams[i][4]), f"beam {i} differs from its single-beam run"
         del ref
+
+
+def test_batch_with_every_launch_group_of_the_three_pass_item(hip_lib):
+    """A batch whose beams fall into more launch groups than there were
+    before the three-pass item ran at M_bin 2048 and 1024 (M_bin 1024, 2048
+    and 4096 x ndec 1, 2, 4, 8 x recurrence / exact transfer function, plus
+    four Stockham groups: 28 groups, more than the 26 sets of work counters
+    the batch workspace held then): each group has its own counters, and
+    every beam equals its single-beam run."""
+    torch = _torch()
+    print("[gpu-case] batch of 28 launch groups", flush=True)
+    specs = []
+    for nchan in (16, 8, 4):                         # M_bin 1024, 2048, 4096 at nfft 16384
+        for ndec in (1, 2, 4, 8):
+            specs.append(BeamSpec(1, 140.0, 16384, 4096, nchan, ndec, 1, [0.0, 0.5, 1.0], "cf32"))
+            specs.append(BeamSpec(1, 140.0, 16384, 4096, nchan, ndec, 1, [0.0, 0.7, 1.1], "cf32"))
+    for nchan in (32, 64):                           # M_bin 512, 256 (Stockham stages)
+        specs.append(BeamSpec(1, 140.0, 16384, 4096, nchan, 2, 1, [0.0, 0.5, 1.0], "cf32"))
+        specs.append(BeamSpec(1, 140.0, 16384, 4096, nchan, 2, 1, [0.0, 0.7, 1.1], "cf32"))
+    beams, _ = _setup(hip_lib, torch, specs)
+    batch = hip_lib.Batch(beams)
+    assert batch.get(hip_lib.CDMT_BATCH_LAUNCHES) == 28
+    batch.run()
+    torch.cuda.synchronize()
+    for i, (sp, (plan, nblock, x, dms, out)) in enumerate(zip(specs, beams)):
+        assert bool(torch.isfinite(out).all()), f"beam {i}: output not fully written"
+        ref = _single(hip_lib, sp, x, hip_lib.cdmt_plan_get(plan.handle, hip_lib.CDMT_OPT_DM_TILE))
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"beam {i} differs from its single-beam run"
