@@ -722,7 +722,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
             tw1[2 * h + 1] = make_float2(x.z, x.w);
         }
         // pass 1
-        cdmt::dft16<+1>(v);
+        cdmt::dft16t<+1>(v);
 #pragma unroll
         for (int k = 1; k < 16; ++k)
             v[k] = cdmt::pmul(v[k], tw1[k]);
@@ -736,7 +736,7 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         for (int r = 0; r < 16; ++r)
             v[r] = x1r[r];
         // pass 2
-        cdmt::dft16<+1>(v);
+        cdmt::dft16t<+1>(v);
         // exchange 2 (across the waves), into this wave's region
         wave_lds_fence();
 #pragma unroll
@@ -756,9 +756,13 @@ __device__ __forceinline__ void dm_item_x3(const FusedArgs &a, DMS dms, int dt, 
         for (int r = 1; r < 16; ++r)
             if (r % P3 != 0)
                 v[r] = cdmt::pmul(v[r], tw2[r]);
+        if constexpr (P3 == 16) {
+            cdmt::dft16t<+1>(v);
+        } else {
 #pragma unroll
-        for (int h = 0; h < 16; h += P3)
-            cdmt::dft<P3, +1>(v + h);
+            for (int h = 0; h < 16; h += P3)
+                cdmt::dft<P3, +1>(v + h);
+        }
 
         // detection: register q holds sample Lc + LC (q / P3) + 256 (q mod P3)
         // (at M = 4096: Lc + 256 q)
@@ -1545,7 +1549,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         for (int q = 0; q < 16; ++q)
             v[q ^ 8] = cdmt::pmul(xs[q], chirp(dm, q));
         // y: pass 1, exchange 1 (within the wave), pass 2, exchange 2
-        cdmt::dft16<+1>(v);
+        cdmt::dft16t<+1>(v);
         twiddle(v, r1, 16, false);
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1554,7 +1558,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
 #pragma unroll
         for (int r = 0; r < 16; ++r)
             v[r] = x1r[r];
-        cdmt::dft16<+1>(v);
+        cdmt::dft16t<+1>(v);
         wave_lds_fence();
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1564,7 +1568,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         for (int r = 0; r < 16; ++r)
             v[r] = x2[kX3Region * (r >> 2) + 272 * (r & 3)];
         twiddle(v, r2, 1, false);
-        cdmt::dft16<+1>(v);
+        cdmt::dft16t<+1>(v);
         // g_y = 2 G y on the kept samples m = L + 256 q
         const float *g = gout + (long long)d * a.ntime_out * a.nch_out +
                          (long long)b * a.tblk * a.t_stride + col * a.col_stride;
@@ -1576,7 +1580,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
             v[q] = cdmt::pscale(v[q], kept ? 2.0f * gi : 0.f);
         }
         // g_x: pass 1 (e-), exchange A (across the waves)
-        cdmt::dft16<-1>(v);
+        cdmt::dft16t<-1>(v);
         twiddle(v, r1b, 16, true);
         __syncthreads();                   // every wave has read exchange 2
 #pragma unroll
@@ -1587,7 +1591,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         for (int r = 0; r < 16; ++r)
             v[r] = xw[16 * r];
         // pass 2, exchange B (within the wave, the slots read in exchange A)
-        cdmt::dft16<-1>(v);
+        cdmt::dft16t<-1>(v);
         wave_lds_fence();
 #pragma unroll
         for (int k = 0; k < 16; ++k)
@@ -1597,7 +1601,7 @@ __global__ __launch_bounds__(256, 2) void dm_grad_x3(FusedArgs a, DmList dl,
         for (int r = 0; r < 16; ++r)
             v[r] = x1r[r];
         twiddle(v, r2b, 1, true);
-        cdmt::dft16<-1>(v);
+        cdmt::dft16t<-1>(v);
         // sum over this lane's bins of g2 Re(conj(g_S') i S'), both pols; the
         // DM is passed through an empty asm so that the compiler evaluates the
         // transfer function here again instead of holding the first one

@@ -205,6 +205,76 @@ __device__ __forceinline__ void dft16(T *a) {
         a[k] = y[k];
 }
 
+// The same 16-point DFT of pairs with the inner twiddles in tangent form:
+// w16^1 = c1 (1 + i S t1), w16^3 = i S c1 (1 - i S t1), w16^9 = -w16^1,
+// w16^2 = c2 (1 + i S), w16^6 = i S w16^2 (c1 = cos(pi/8), t1 = tan(pi/8),
+// c2 = 1/sqrt(2)): the rotations by (1 +- i S t1) are two fused multiply-adds
+// per complex value and (1 + i S) two additions, and the common factors c1
+// and c2 of a row ride in the fused multiply-adds of its second-stage
+// butterflies, so no multiplication is spent on them (144 instead of 160
+// operations per complex transform).
+template <int S>
+__device__ __forceinline__ cpair rot_t(cpair z, float t) {   // z (1 + i S t)
+    const float st = S > 0 ? t : -t;
+    return make_float4(fmaf(-st, z.y, z.x), fmaf(st, z.x, z.y), fmaf(-st, z.w, z.z),
+                       fmaf(st, z.z, z.w));
+}
+template <int S>
+__device__ __forceinline__ cpair rot_1(cpair z) {            // z (1 + i S)
+    if constexpr (S > 0)
+        return make_float4(z.x - z.y, z.y + z.x, z.z - z.w, z.w + z.z);
+    else
+        return make_float4(z.x + z.y, z.y - z.x, z.z + z.w, z.w - z.z);
+}
+__device__ __forceinline__ cpair pfma(cpair p, float c, cpair q) {   // p + c q
+    return make_float4(fmaf(c, q.x, p.x), fmaf(c, q.y, p.y), fmaf(c, q.z, p.z), fmaf(c, q.w, p.w));
+}
+template <int S>
+__device__ __forceinline__ void dft16t(cpair *a) {
+    constexpr float c1 = 0.92387953251128674f, t1 = 0.41421356237309505f;
+    constexpr float c2 = 0.70710678118654752f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+        dft4<S>(a[e], a[e + 4], a[e + 8], a[e + 12]);
+    dft4<S>(a[0], a[1], a[2], a[3]);
+    {   // row 1: twiddles w^1, w^2, w^3
+        const cpair r5 = rot_t<S>(a[5], t1), q6 = rot_1<S>(a[6]), r7 = rot_t<S>(a[7], -t1);
+        const cpair s02 = pfma(a[4], c2, q6), d02 = pfma(a[4], -c2, q6);
+        const cpair u = padd(r5, pmuli<S>(r7)), v = padd(pmuli<S>(r5), r7);
+        a[4] = pfma(s02, c1, u);
+        a[6] = pfma(s02, -c1, u);
+        a[5] = pfma(d02, c1, v);
+        a[7] = pfma(d02, -c1, v);
+    }
+    {   // row 2: w^2, w^4 = i S, w^6
+        const cpair q9 = rot_1<S>(a[9]), q11 = rot_1<S>(a[11]), i10 = pmuli<S>(a[10]);
+        const cpair s02 = padd(a[8], i10), d02 = psub(a[8], i10);
+        const cpair u = padd(q9, pmuli<S>(q11)), v = padd(pmuli<S>(q9), q11);
+        a[8] = pfma(s02, c2, u);
+        a[10] = pfma(s02, -c2, u);
+        a[9] = pfma(d02, c2, v);
+        a[11] = pfma(d02, -c2, v);
+    }
+    {   // row 3: w^3, w^6, w^9
+        const cpair r13 = rot_t<S>(a[13], -t1), q14 = rot_1<S>(a[14]), r15 = rot_t<S>(a[15], t1);
+        const cpair iq14 = pmuli<S>(q14);
+        const cpair s02 = pfma(a[12], c2, iq14), d02 = pfma(a[12], -c2, iq14);
+        const cpair u = psub(pmuli<S>(r13), r15), v = psub(pmuli<S>(r15), r13);
+        a[12] = pfma(s02, c1, u);
+        a[14] = pfma(s02, -c1, u);
+        a[13] = pfma(d02, c1, v);
+        a[15] = pfma(d02, -c1, v);
+    }
+    // y[k] sits at a[4 (k mod 4) + k / 4]: transpose the 4x4 block
+    cpair y[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        y[k] = a[4 * (k & 3) + (k >> 2)];
+#pragma unroll
+    for (int k = 0; k < 16; ++k)
+        a[k] = y[k];
+}
+
 template <int R, int S, class T>
 __device__ __forceinline__ void dft(T *a) {
     if constexpr (R == 16)
